@@ -1,0 +1,233 @@
+/*
+ * otbb.h -- C ABI of the MI355X interior-point solver for finite-volume
+ * dynamical (Benamou-Brenier) optimal transport.
+ *
+ * Paper: E. Facca, G. Todeschi, A. Natale, M. Benzi, "Efficient
+ * preconditioners for solving dynamical optimal transport via interior point
+ * methods", arXiv 2209.00315.
+ *
+ * The problem (Sec. 1 and Sec. 2): given two densities rho_in, rho_f of equal
+ * mass on a polygonal domain, find the time-dependent density rho, the
+ * potential phi and the slack s solving the relaxed discrete optimality
+ * system (Sec. 2.3-2.4) on a two-level finite-volume mesh with staggered
+ * time levels: K density levels, K+1 potential levels, dt = 1/(K+1).
+ * Each interior-point step runs inexact Newton iterations; each Newton
+ * system is the projected saddle-point system of Sec. 4.4.2, solved by
+ * flexible GMRES preconditioned by the BB block-triangular preconditioner of
+ * Sec. 4.4.3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: 0 on success, a negative OT_E* code on failure.  No C++
+ *    exception crosses this boundary; ot_last_error() gives a message.
+ *  - Ownership: the caller owns every array it passes; the library copies
+ *    inputs in and writes outputs to caller memory.  Handles (ot_mesh,
+ *    ot_state) are library-owned; destroy them with the matching call.
+ *    A handle must not be used from two threads at once.
+ *  - Memory kind: with ot_options.mem_kind == OT_HOST every vector pointer is
+ *    host memory; with OT_DEVICE it is device memory of the current HIP
+ *    device (e.g. a torch tensor's data_ptr), read and written on
+ *    ot_options.stream (NULL = the null stream).  Mesh descriptions are
+ *    always host memory.
+ *  - Layout: all vectors are FP64, slice-major.  phi has (K+1) * n_fine
+ *    entries (level k at offset k * n_fine), rho and s have K * n_coarse.
+ *    A "saddle vector" of length N = (K+1) n_fine + K n_coarse is the phi
+ *    block followed by the rho block.
+ *  - Errors leave handles usable and in their state before the call, except
+ *    OT_ELINSOLVE / OT_ENEWTON from ot_newton_step and ot_solve, which leave
+ *    the last accepted iterate in the state.
+ */
+#ifndef OTBB_H
+#define OTBB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define OT_OK          0
+#define OT_EINVAL     -1   /* null pointer, bad size or bad option          */
+#define OT_EMESH      -2   /* area or distance <= 0, bad index, overlaps not
+                              summing to the cell areas                     */
+#define OT_EMASS      -3   /* |a'.rho_in - a'.rho_f| > 1e-12 a'.rho_in       */
+#define OT_ENEG       -4   /* negative or non-finite marginal                */
+#define OT_ELINSOLVE  -5   /* FGMRES did not reach its tolerance             */
+#define OT_ENEWTON    -6   /* Newton iteration cap reached at some mu        */
+#define OT_EDEVICE    -7   /* HIP runtime error                              */
+#define OT_ENOMEM     -8   /* device or host allocation failed               */
+
+#define OT_FP64   0        /* every kernel in FP64                           */
+#define OT_MIXED  1        /* preconditioner in FP32, the rest in FP64       */
+
+#define OT_HOST   0
+#define OT_DEVICE 1
+
+typedef struct ot_mesh  ot_mesh;    /* opaque, immutable after creation      */
+typedef struct ot_state ot_state;   /* opaque: (phi, rho, s, mu) + workspaces */
+
+/*
+ * Generic two-level FV mesh (Sec. 2.1).  Host arrays, copied in.
+ *  fine cells carry phi, coarse cells carry rho and s.
+ *  Omega = M J is given by its nonzeros (ov_fine[t], ov_coarse[t], ov_area[t]):
+ *    rows must sum to fine_area, columns to coarse_area (relative 1e-10).
+ *  Fine interior edges e: fe_cell[2e] = K, fe_cell[2e+1] = L with
+ *    E(K,e) = +1, E(L,e) = -1, grad phi_e = (phi_K - phi_L) / fe_dist[e];
+ *    fe_rho[2e], fe_rho[2e+1] = coarse cells feeding the density
+ *    reconstruction R_E on the K and L side, with weights fe_lambda[e] and
+ *    1 - fe_lambda[e].  Boundary edges are omitted (no-flux).
+ *  Coarse interior edges (ce_*) define the coarse Laplacian of the BB
+ *    approximation (Sec. 4.4.3); they never change the solution.
+ *  All lengths and distances must be > 0 and lambdas in [0, 1].
+ */
+typedef struct {
+    int32_t n_fine, n_coarse;
+    const double *fine_area, *coarse_area;
+    int32_t n_overlap;
+    const int32_t *ov_fine, *ov_coarse;
+    const double *ov_area;
+    int32_t n_fedge;
+    const int32_t *fe_cell;      /* [2 * n_fedge] */
+    const int32_t *fe_rho;       /* [2 * n_fedge] */
+    const double *fe_len, *fe_dist, *fe_lambda;
+    int32_t n_cedge;
+    const int32_t *ce_cell;      /* [2 * n_cedge] */
+    const double *ce_len, *ce_dist, *ce_lambda;
+} ot_mesh_desc;
+
+/*
+ * Solver options; ot_options_default() fills the paper's settings:
+ *  tol 1e-6 (Newton, absolute Euclidean norm of (F_phi; F_rho; F_s - mu),
+ *  Sec. 2.4), eps_out 1e-5 (FGMRES, relative to |(f;g;h)|, Sec. 3.1),
+ *  eps_in_S 1e-1 (pseudo-Schur inner solve, Sec. 4.4.4), eps_in_A 1e-2
+ *  (Laplacian inner solves; the paper's 5e-2 was tuned for its AMG),
+ *  mu0 1, mu_factor 0.2, step fraction 0.99, caps 400 FGMRES / 200 inner /
+ *  20 Newton, restart 40, OT_MIXED, OT_HOST, null stream.
+ */
+typedef struct {
+    double tol, eps_out, eps_in_S, eps_in_A;
+    double mu0, mu_factor, frac_to_boundary;
+    double final_tol;        /* <= 0: use tol for the last mu as well       */
+    int32_t max_fgmres, restart, max_inner, max_newton, inner_restart;
+    int32_t precision, mem_kind;
+    int32_t verbose;
+    void *stream;            /* hipStream_t */
+} ot_options;
+
+/* Per-solve statistics (the paper's Outer/Lin.sys, Inner/Outer metrics). */
+typedef struct {
+    int32_t ip_steps, newton_steps, linear_systems;
+    int64_t outer_iters, inner_S_iters, inner_A_iters, prec_applies;
+    int32_t failures;        /* linear solves that missed eps_out           */
+    double seconds_total, seconds_linear, seconds_setup;
+    double final_residual, mu;
+    double cost, dual, gap;
+} ot_stats;
+
+void ot_options_default(ot_options *opt);
+
+/* Create a mesh from a generic description.  Errors: OT_EINVAL, OT_EMESH. */
+int  ot_mesh_create(const ot_mesh_desc *desc, ot_mesh **out);
+/* The n x n right-triangle grid (n even >= 2): phi on the n^2 squares (the
+ * two triangles of a square share a circumcentre, so their potentials are
+ * tied), rho on the 2 (n/2)^2 coarse triangles; index conventions
+ * fine i = b n + a, coarse j = 2 (B n/2 + A) + t, t = 0 below the SW-NE
+ * diagonal.  cartesian = 1 instead gives the single n x n Cartesian grid
+ * (J = identity).  Errors: OT_EINVAL. */
+int  ot_mesh_create_structured(int32_t n, int32_t cartesian, ot_mesh **out);
+void ot_mesh_destroy(ot_mesh *mesh);
+int  ot_mesh_sizes(const ot_mesh *mesh, int32_t *n_fine, int32_t *n_coarse,
+                   int32_t *n_fedge, int32_t *n_cedge);
+
+/*
+ * Full interior-point solve (Sec. 2.4): mu_l = mu0 mu_factor^l, inexact
+ * Newton until |F_mu| <= tol at each mu, stop after the first mu < tol.
+ * Outputs: rho_out [K n_coarse], phi_out [(K+1) n_fine] shifted so that
+ * sum_k a^T phi^k = 0, cost_out = discrete kinetic energy.  Any output
+ * pointer may be NULL.  stats may be NULL.
+ * Errors: OT_EINVAL, OT_EMASS, OT_ENEG, OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE,
+ * OT_ENOMEM.
+ */
+int  ot_solve(const ot_mesh *mesh, const double *rho_in, const double *rho_f,
+              int32_t K, double tol, const ot_options *opt,
+              double *rho_out, double *phi_out, double *cost_out, ot_stats *stats);
+
+/*
+ * Solve nprob independent problems (meshes and K may differ) with one
+ * device state per problem, interleaving their kernels on the same stream.
+ * Arrays of pointers have nprob entries; costs[nprob]; stats[nprob] or NULL.
+ */
+int  ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes,
+                      const double *const *rho_in, const double *const *rho_f,
+                      const int32_t *K, double tol, const ot_options *opt,
+                      double *const *rho_out, double *const *phi_out,
+                      double *costs, ot_stats *stats);
+
+/*
+ * Create a state: validates the marginals (OT_ENEG, OT_EMASS) and sets the
+ * start point phi = 0, rho = m0 / |Omega|, s = mu0 / rho, mu = mu0.
+ */
+int  ot_state_create(const ot_mesh *mesh, const double *rho_in, const double *rho_f,
+                     int32_t K, const ot_options *opt, ot_state **out);
+void ot_state_destroy(ot_state *st);
+int  ot_state_sizes(const ot_state *st, int64_t *n_phi, int64_t *m_rho);
+/* Copy (phi, rho, s, mu) out / in (any pointer may be NULL on export). */
+int  ot_state_export(const ot_state *st, double *phi, double *rho, double *s, double *mu);
+int  ot_state_import(ot_state *st, const double *phi, const double *rho,
+                     const double *s, double mu);
+/* Set mu without touching (phi, rho, s). */
+int  ot_state_set_mu(ot_state *st, double mu);
+/* Residual (F_phi; F_rho; F_s - mu) of Sec. 2.3-2.4 at the current state,
+ * written to F [(K+1) n_fine + 2 K n_coarse] (may be NULL); norm to *nrm. */
+int  ot_residual(ot_state *st, double *F, double *nrm);
+
+/*
+ * One inexact Newton step at the current mu: residual, linearisation, FGMRES
+ * on the projected system with the BB preconditioner, recovery of
+ * (delta phi, delta rho, delta s) (Sec. 4.4.1-4.4.2, Sec. 3.1), positivity
+ * line search with the step fraction, update, per-slice renormalisation of
+ * rho.  *res_norm (may be NULL) receives |F_mu| before the step.
+ * Errors: OT_ELINSOLVE (step still taken if the residual dropped below 1e-2
+ * of the right-hand side), OT_EDEVICE.
+ */
+int  ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm);
+
+/*
+ * y = J_P x: the projected saddle operator of Sec. 4.4.2 linearised at the
+ * current state, J_P = [[A, B^T P^T], [P B, -P C P^T]].  x, y: length N.
+ */
+int  ot_apply_saddle(ot_state *st, const double *x, double *y);
+
+/*
+ * z = P_BB^-1 r: one application of the BB preconditioner (Sec. 4.4.3)
+ * linearised at the current state: pseudo-Schur solve
+ * (Diag(s) A~ - Diag(rho) B M^-1 B~) w = -Diag(rho) P r_rho, then
+ * z_rho = P^T M'^-1 A~ w, then the K+1 Laplacian solves
+ * A^k z_phi^k = (r_phi - B^T z_rho)^k projected to zero sum; z_phi^k is
+ * returned with zero sum.  Inner tolerances come from the state's options;
+ * set eps_in_S and eps_in_A to ~1e-13 for (near-)exact inner solves.
+ */
+int  ot_apply_schur_prec(ot_state *st, const double *r, double *z);
+
+/*
+ * Gradient of the transport cost at the current (converged) state with
+ * respect to rho_in and rho_f (envelope term plus one adjoint saddle solve),
+ * projected orthogonal to the coarse areas a'.  g_in, g_f: n_coarse each.
+ */
+int  ot_gradient(ot_state *st, double *g_in, double *g_f);
+
+/* Outputs at the current state: cost (kinetic energy), dual value D*, and
+ * phi normalised so that sum_k a^T phi^k = 0 (phi_out may be NULL). */
+int  ot_outputs(ot_state *st, double *cost, double *dual, double *phi_out);
+
+/* Change options of an existing state (tolerances, precision, caps). */
+int  ot_state_set_options(ot_state *st, const ot_options *opt);
+
+/* Message of the last error on this thread (never NULL). */
+const char *ot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTBB_H */

@@ -1,0 +1,65 @@
+/*
+ * otbb_debug.h -- host-only inspection entry points of the otbb library.
+ *
+ * They run the mesh generator, the validation and the derivation of the
+ * index structures (multigrid aggregation, coarse-cell coloring) on the host
+ * and never touch a device, so host logic can be checked without a GPU.
+ * Same error codes and ownership rules as otbb.h.
+ */
+#ifndef OTBB_DEBUG_H
+#define OTBB_DEBUG_H
+
+#include "otbb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out = {n_fine, n_coarse, n_fedge, n_cedge, n_overlap, multigrid levels,
+ *        coarse-cell colors, fine-cell ELL width} of the structured mesh of
+ * ot_mesh_create_structured(n, cartesian).  Errors: OT_EINVAL. */
+int otbb_debug_structured_sizes(int32_t n, int32_t cartesian, int32_t out[8]);
+
+/* Copy the arrays of that mesh into caller buffers sized from
+ * otbb_debug_structured_sizes (any pointer may be NULL): fine edges
+ * (cells, density sides, length, distance, lambda), overlaps, coarse edges
+ * (cells, length, distance) and the coarse-cell coloring. */
+int otbb_debug_structured_arrays(int32_t n, int32_t cartesian, int32_t *fe_cell, int32_t *fe_rho,
+                                 double *fe_len, double *fe_dist, double *fe_lambda, int32_t *ov_fine,
+                                 int32_t *ov_coarse, double *ov_area, int32_t *ce_cell, double *ce_len,
+                                 double *ce_dist, int32_t *color);
+
+/* Validate a mesh description and derive its structures on the host only.
+ * Returns OT_OK, OT_EINVAL or OT_EMESH exactly as ot_mesh_create would
+ * before its device upload. */
+int otbb_debug_validate_desc(const ot_mesh_desc *desc);
+
+/*
+ * Components of the BB preconditioner at the state's current linearisation
+ * (built on first use), host pointers in and out, FP64 at the interface and
+ * the state's precision inside:
+ *  schur_apply:   out = (Diag(s) A~ - Diag(rho) B M^-1 B~) z      (m_rho)
+ *  schur_solve:   right-preconditioned restarted GMRES on that system,
+ *                 relative tolerance tol, cap maxit, iterations to *iters
+ *  tri_diagonals: its three time diagonals per coarse cell (probed):
+ *                 d0 = (k,k), dl = (k,k-1), du = (k,k+1) entries (m_rho)
+ *  laplace_solve: PCG with the multigrid V-cycle on the K+1 Laplacians
+ *                 A^k x^k = b^k (b zero-sum per slice)             (n_phi)
+ *  vcycle:        one multigrid V-cycle x = M^-1 b on all slices  (n_phi)
+ */
+int otbb_debug_schur_apply(ot_state *st, const double *z, double *out);
+int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double tol, int32_t maxit,
+                           int32_t *iters);
+int otbb_debug_tri_diagonals(ot_state *st, double *d0, double *dl, double *du);
+int otbb_debug_laplace_solve(ot_state *st, const double *b, double *x, double tol, int32_t maxit,
+                             int32_t *iters);
+int otbb_debug_vcycle(ot_state *st, const double *b, double *x);
+/* Multigrid level data of the current linearisation: what = 0 edge weights
+ * [(K+1) x edges of the level], what = 1 inverse diagonals [(K+1) x cells].
+ * *count receives the length; out may be NULL to query it. */
+int otbb_debug_mg_level(ot_state *st, int32_t level, int32_t what, double *out, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTBB_DEBUG_H */

@@ -220,3 +220,21 @@ def cartesian_mesh(n: int) -> Mesh:
         ce_lam=np.full(ne, 0.5),
         name=f"cartesian{n}",
     )
+
+
+def mesh_from_arrays(d, name="generic") -> Mesh:
+    """Oracle Mesh from the arrays of a generic mesh description."""
+    fe = np.asarray(d["fe_cell"], dtype=np.int64).reshape(-1, 2)
+    fr = np.asarray(d["fe_rho"], dtype=np.int64).reshape(-1, 2)
+    ce = np.asarray(d["ce_cell"], dtype=np.int64).reshape(-1, 2)
+    return Mesh(
+        n_fine=len(d["fine_area"]), n_coarse=len(d["coarse_area"]),
+        fine_area=np.asarray(d["fine_area"], float), coarse_area=np.asarray(d["coarse_area"], float),
+        ov_fine=np.asarray(d["ov_fine"], np.int64), ov_coarse=np.asarray(d["ov_coarse"], np.int64),
+        ov_area=np.asarray(d["ov_area"], float),
+        fe_K=fe[:, 0].copy(), fe_L=fe[:, 1].copy(), fe_rK=fr[:, 0].copy(), fe_rL=fr[:, 1].copy(),
+        fe_len=np.asarray(d["fe_len"], float), fe_dist=np.asarray(d["fe_dist"], float),
+        fe_lam=np.asarray(d["fe_lambda"], float),
+        ce_i=ce[:, 0].copy(), ce_j=ce[:, 1].copy(), ce_len=np.asarray(d["ce_len"], float),
+        ce_dist=np.asarray(d["ce_dist"], float), ce_lam=np.asarray(d["ce_lambda"], float),
+        name=name)

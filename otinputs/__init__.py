@@ -180,3 +180,70 @@ def mass_preserving_directions(rho, areas, count, seed):
         d = rho * xi - rho * float(areas @ (rho * xi)) / float(areas @ rho)
         out.append(d / np.linalg.norm(d))
     return np.array(out)
+
+
+def random_mesh_arrays(nf, nc, seed):
+    """A random, valid generic two-level mesh description (graph-based, not
+    geometric) for exercising the generic mesh interface: positive areas,
+    overlaps summing to both cell areas, a connected fine edge graph with
+    random lengths, distances and lambdas, density sides taken among the
+    parents of each edge cell, and coarse edges between parents of
+    neighbouring fine cells."""
+    rng = np.random.default_rng(seed)
+    assert nf >= nc >= 2
+    parent = np.concatenate([np.arange(nc), rng.integers(0, nc, nf - nc)])
+    rng.shuffle(parent)
+    ov = {}
+    for i in range(nf):
+        ov[(i, int(parent[i]))] = rng.uniform(0.5, 1.5)
+        if rng.random() < 0.3:
+            j2 = int(rng.integers(0, nc))
+            if j2 != parent[i]:
+                ov[(i, j2)] = rng.uniform(0.2, 0.8)
+    keys = sorted(ov)
+    ov_f = np.array([k[0] for k in keys], dtype=np.int32)
+    ov_c = np.array([k[1] for k in keys], dtype=np.int32)
+    ov_a = np.array([ov[k] for k in keys])
+    ov_a /= ov_a.sum()
+    fine_area = np.bincount(ov_f, weights=ov_a, minlength=nf)
+    coarse_area = np.bincount(ov_c, weights=ov_a, minlength=nc)
+    parents = [[] for _ in range(nf)]
+    for f, c in zip(ov_f, ov_c):
+        parents[f].append(int(c))
+    perm = rng.permutation(nf)
+    edges = set()
+    for t in range(1, nf):
+        a, b = int(perm[t]), int(perm[rng.integers(0, t)])
+        edges.add((min(a, b), max(a, b)))
+    while len(edges) < 2 * nf:
+        a, b = rng.integers(0, nf, 2)
+        if a != b:
+            edges.add((int(min(a, b)), int(max(a, b))))
+    edges = sorted(edges)
+    ne = len(edges)
+    fe_cell = np.array(edges, dtype=np.int32).ravel()
+    fe_rho = np.array([[parents[a][rng.integers(len(parents[a]))], parents[b][rng.integers(len(parents[b]))]]
+                       for a, b in edges], dtype=np.int32).ravel()
+    scale = 1.0 / np.sqrt(nf)
+    fe_len = rng.uniform(0.5, 1.5, ne) * scale
+    fe_dist = rng.uniform(0.5, 1.5, ne) * scale
+    fe_lambda = rng.uniform(0.0, 1.0, ne)
+    cset = set()
+    for a, b in edges:
+        for ca in parents[a]:
+            for cb in parents[b]:
+                if ca != cb:
+                    cset.add((min(ca, cb), max(ca, cb)))
+    cperm = rng.permutation(nc)
+    for t in range(1, nc):
+        a, b = int(cperm[t]), int(cperm[rng.integers(0, t)])
+        cset.add((min(a, b), max(a, b)))
+    cedges = sorted(cset)
+    nce = len(cedges)
+    return dict(
+        fine_area=fine_area, coarse_area=coarse_area, ov_fine=ov_f, ov_coarse=ov_c, ov_area=ov_a,
+        fe_cell=fe_cell, fe_rho=fe_rho, fe_len=fe_len, fe_dist=fe_dist, fe_lambda=fe_lambda,
+        ce_cell=np.array(cedges, dtype=np.int32).ravel(),
+        ce_len=rng.uniform(0.5, 1.5, nce) * np.sqrt(2.0 / nc),
+        ce_dist=rng.uniform(0.5, 1.5, nce) * np.sqrt(2.0 / nc),
+        ce_lambda=rng.uniform(0.0, 1.0, nce))

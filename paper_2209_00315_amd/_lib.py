@@ -1,0 +1,131 @@
+"""ctypes declarations of the otbb C ABI (include/otbb.h, include/otbb_debug.h).
+
+Argument marshalling only: every step of the solver runs in libotbb.so.
+Loading fails loudly when the library has not been built.
+"""
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libotbb.so")
+
+OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG = 0, -1, -2, -3, -4
+OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM = -5, -6, -7, -8
+OT_FP64, OT_MIXED = 0, 1
+OT_HOST, OT_DEVICE = 0, 1
+
+ERROR_NAMES = {
+    OT_EINVAL: "OT_EINVAL", OT_EMESH: "OT_EMESH", OT_EMASS: "OT_EMASS", OT_ENEG: "OT_ENEG",
+    OT_ELINSOLVE: "OT_ELINSOLVE", OT_ENEWTON: "OT_ENEWTON", OT_EDEVICE: "OT_EDEVICE",
+    OT_ENOMEM: "OT_ENOMEM",
+}
+
+dptr = C.POINTER(C.c_double)
+iptr = C.POINTER(C.c_int32)
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double), ("eps_out", C.c_double), ("eps_in_S", C.c_double), ("eps_in_A", C.c_double),
+        ("mu0", C.c_double), ("mu_factor", C.c_double), ("frac_to_boundary", C.c_double),
+        ("final_tol", C.c_double),
+        ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
+        ("max_newton", C.c_int32), ("inner_restart", C.c_int32),
+        ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("ip_steps", C.c_int32), ("newton_steps", C.c_int32), ("linear_systems", C.c_int32),
+        ("outer_iters", C.c_int64), ("inner_S_iters", C.c_int64), ("inner_A_iters", C.c_int64),
+        ("prec_applies", C.c_int64), ("failures", C.c_int32),
+        ("seconds_total", C.c_double), ("seconds_linear", C.c_double), ("seconds_setup", C.c_double),
+        ("final_residual", C.c_double), ("mu", C.c_double),
+        ("cost", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [
+        ("n_fine", C.c_int32), ("n_coarse", C.c_int32),
+        ("fine_area", dptr), ("coarse_area", dptr),
+        ("n_overlap", C.c_int32), ("ov_fine", iptr), ("ov_coarse", iptr), ("ov_area", dptr),
+        ("n_fedge", C.c_int32), ("fe_cell", iptr), ("fe_rho", iptr),
+        ("fe_len", dptr), ("fe_dist", dptr), ("fe_lambda", dptr),
+        ("n_cedge", C.c_int32), ("ce_cell", iptr), ("ce_len", dptr), ("ce_dist", dptr), ("ce_lambda", dptr),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "ot_options_default": (None, [C.POINTER(Options)]),
+    "ot_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
+    "ot_mesh_create_structured": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    "ot_mesh_destroy": (None, [C.c_void_p]),
+    "ot_mesh_sizes": (C.c_int, [C.c_void_p, iptr, iptr, iptr, iptr]),
+    "ot_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(Options),
+                           C.c_void_p, C.c_void_p, dptr, C.POINTER(Stats)]),
+    "ot_solve_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), iptr, C.c_double, C.POINTER(Options),
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), dptr, C.POINTER(Stats)]),
+    "ot_state_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Options),
+                                  C.POINTER(C.c_void_p)]),
+    "ot_state_destroy": (None, [C.c_void_p]),
+    "ot_state_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "ot_state_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dptr]),
+    "ot_state_import": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "ot_state_set_mu": (C.c_int, [C.c_void_p, C.c_double]),
+    "ot_state_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
+    "ot_residual": (C.c_int, [C.c_void_p, C.c_void_p, dptr]),
+    "ot_newton_step": (C.c_int, [C.c_void_p, C.POINTER(Stats), dptr]),
+    "ot_apply_saddle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ot_apply_schur_prec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ot_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ot_outputs": (C.c_int, [C.c_void_p, dptr, dptr, C.c_void_p]),
+    "ot_last_error": (C.c_char_p, []),
+    "otbb_debug_structured_sizes": (C.c_int, [C.c_int32, C.c_int32, iptr]),
+    "otbb_debug_structured_arrays": (C.c_int, [C.c_int32, C.c_int32, iptr, iptr, dptr, dptr, dptr,
+                                               iptr, iptr, dptr, iptr, dptr, dptr, iptr]),
+    "otbb_debug_validate_desc": (C.c_int, [C.POINTER(MeshDesc)]),
+    "otbb_debug_schur_apply": (C.c_int, [C.c_void_p, dptr, dptr]),
+    "otbb_debug_schur_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
+    "otbb_debug_tri_diagonals": (C.c_int, [C.c_void_p, dptr, dptr, dptr]),
+    "otbb_debug_laplace_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
+    "otbb_debug_vcycle": (C.c_int, [C.c_void_p, dptr, dptr]),
+    "otbb_debug_mg_level": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, dptr, C.POINTER(C.c_int64)]),
+}
+
+
+def lib():
+    """Load libotbb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libotbb.so not built at {LIB_PATH}; run paper_2209_00315_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class OTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code):
+    if code != OT_OK:
+        raise OTError(code, lib().ot_last_error().decode())
+    return code

@@ -1,0 +1,847 @@
+// Device kernels of the otbb library (gfx950, wave64).
+//
+// Index conventions: fine cell i in [0, nf), potential level k in [0, K]
+// (the paper's levels 1..K+1), coarse cell j in [0, nc), density level k in
+// [0, K) (the paper's 1..K).  Density "time indices" L in [0, K+1] address
+// (rho_in, rho^1..rho^K, rho_f).  Potential level k sits between density
+// indices L = k and L = k + 1.  All per-slice topology arrays are ELL,
+// column-major (t * n + cell), padded with -1; they are the same for every
+// time slice, so one launch covers all slices (blockIdx.y = slice) and the
+// topology is read from cache after the first slice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cstdint>
+
+namespace otbb {
+namespace kern {
+
+constexpr int BS = 256;
+
+struct MeshView {
+    int nf, nc, ne, nce, wf, wo, woc, wr, wcc;
+    const double *a, *ac, *elam, *etw, *eW, *einvd, *elen, *cetw, *celam, *fo_w, *co_w, *cr_w;
+    const int *eK, *eL, *erK, *erL, *ceI, *ceJ, *cf_edge, *cf_nb, *fo_c, *co_f, *cr_e, *cc_edge, *cc_nb;
+};
+
+struct StateView {
+    int K;
+    double dt, area;
+    const double *phi, *rho, *s, *rin, *rf;
+};
+
+// ---------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[BS / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    v = (threadIdx.x < BS / 64) ? sh[threadIdx.x] : 0.0;
+    if (wid == 0) v = wave_sum(v);
+    return v;
+}
+
+__device__ __forceinline__ double block_min(double v) {
+    __shared__ double sh[BS / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    v = (threadIdx.x < BS / 64) ? sh[threadIdx.x] : DBL_MAX;
+    if (wid == 0) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    }
+    return v;
+}
+
+// out[seg] = sum_b part[seg * nblk + b]   (one block per segment)
+__global__ void k_seg_final(const double *__restrict__ part, int nblk, double *__restrict__ out) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += BS) v += part[(size_t)blockIdx.x * nblk + b];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+__global__ void k_min_final(const double *__restrict__ part, int nblk, double *__restrict__ out) {
+    double v = DBL_MAX;
+    for (int b = threadIdx.x; b < nblk; b += BS) v = fmin(v, part[b]);
+    v = block_min(v);
+    if (threadIdx.x == 0) out[0] = v;
+}
+
+// Segmented (weighted) sums: part[seg * nblk + b] over x[seg * n + i] * w[i].
+template <typename T>
+__global__ void k_seg_partial(const T *__restrict__ x, const double *__restrict__ w, int n,
+                              double *__restrict__ part) {
+    const int seg = blockIdx.y;
+    double v = 0.0;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
+        double xi = (double)x[(size_t)seg * n + i];
+        v += w ? w[i] * xi : xi;
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[(size_t)seg * gridDim.x + blockIdx.x] = v;
+}
+
+// Segmented dot products: part[seg * nblk + b] of sum_i x * y over segment seg.
+template <typename T>
+__global__ void k_seg_dot_partial(const T *__restrict__ x, const T *__restrict__ y, int n,
+                                  double *__restrict__ part) {
+    const int seg = blockIdx.y;
+    double v = 0.0;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
+        size_t q = (size_t)seg * n + i;
+        v += (double)x[q] * (double)y[q];
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[(size_t)seg * gridDim.x + blockIdx.x] = v;
+}
+
+// ----------------------------------------------------------- state helpers
+__device__ __forceinline__ double rho_at(const StateView &S, int nc, int L, int j) {
+    return L == 0 ? S.rin[j] : (L == S.K + 1 ? S.rf[j] : S.rho[(size_t)(L - 1) * nc + j]);
+}
+
+// rho~ on fine edge e at potential level k: R_E((rho^L + rho^{L+1})/2), L = k
+__device__ __forceinline__ double rho_edge(const MeshView &m, const StateView &S, int k, int e) {
+    const int rK = m.erK[e], rL = m.erL[e];
+    const double lam = m.elam[e];
+    const double mK = 0.5 * (rho_at(S, m.nc, k, rK) + rho_at(S, m.nc, k + 1, rK));
+    const double mL = 0.5 * (rho_at(S, m.nc, k, rL) + rho_at(S, m.nc, k + 1, rL));
+    return lam * mK + (1.0 - lam) * mL;
+}
+
+__device__ __forceinline__ double grad_phi(const MeshView &m, const double *ph, int e) {
+    return (ph[m.eK[e]] - ph[m.eL[e]]) * m.einvd[e];
+}
+
+// ------------------------------------------------------------- residual F
+// F_phi^k = -Omega (rho^{k+1} - rho^k)/dt + sum_e tw rho~ (phi_i - phi_nb)
+__global__ void k_res_phi(MeshView m, StateView S, double *__restrict__ F, double *__restrict__ part) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double sq = 0.0;
+    if (i < m.nf) {
+        const double *ph = S.phi + (size_t)k * m.nf;
+        double v = 0.0;
+        for (int t = 0; t < m.wo; ++t) {
+            const int c = m.fo_c[t * m.nf + i];
+            if (c < 0) break;
+            v -= m.fo_w[t * m.nf + i] * (rho_at(S, m.nc, k + 1, c) - rho_at(S, m.nc, k, c)) / S.dt;
+        }
+        const double pi = ph[i];
+        for (int t = 0; t < m.wf; ++t) {
+            const int e = m.cf_edge[t * m.nf + i];
+            if (e < 0) break;
+            v += m.etw[e] * rho_edge(m, S, k, e) * (pi - ph[m.cf_nb[t * m.nf + i]]);
+        }
+        F[(size_t)k * m.nf + i] = v;
+        sq = v * v;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sq;
+}
+
+// F_rho^k = Omega^T (phi^{k+1} - phi^k)/dt + 1/4 R_T(g_k^2 + g_{k+1}^2) + a' s;  F_s = rho s - mu
+__global__ void k_res_rho(MeshView m, StateView S, double mu, double *__restrict__ Frho,
+                          double *__restrict__ Fs, double *__restrict__ part) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double sq = 0.0;
+    if (j < m.nc) {
+        const double *p0 = S.phi + (size_t)k * m.nf, *p1 = p0 + m.nf;
+        double v = 0.0;
+        for (int t = 0; t < m.woc; ++t) {
+            const int f = m.co_f[t * m.nc + j];
+            if (f < 0) break;
+            v += m.co_w[t * m.nc + j] * (p1[f] - p0[f]) / S.dt;
+        }
+        double hj = 0.0;
+        for (int t = 0; t < m.wr; ++t) {
+            const int e = m.cr_e[t * m.nc + j];
+            if (e < 0) break;
+            const double g0 = grad_phi(m, p0, e), g1 = grad_phi(m, p1, e);
+            hj += m.cr_w[t * m.nc + j] * (g0 * g0 + g1 * g1);
+        }
+        const size_t q = (size_t)k * m.nc + j;
+        v += 0.25 * hj + m.ac[j] * S.s[q];
+        const double fs = S.rho[q] * S.s[q] - mu;
+        Frho[q] = v;
+        Fs[q] = fs;
+        sq = v * v + fs * fs;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sq;
+}
+
+// ------------------------------------------------------ saddle operator J_P
+// value of (P^T x_rho) at density level l (0-based), zero outside [0, K)
+__device__ __forceinline__ double ptx_at(const double *xr, const double *cs, double area, int K, int nc,
+                                         int l, int j) {
+    return (l >= 0 && l < K) ? xr[(size_t)l * nc + j] - cs[l] / area : 0.0;
+}
+
+// y_phi^k = A^k x_phi^k + (B^T w)^k with w = P^T x_rho, cs[l] = a'^T x_rho^l:
+// (B^T w)^k = Omega (w^{k-1} - w^k)/dt + 1/2 sum_e sgn len g_e R_E(w^{k-1} + w^k)_e
+__global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__ x,
+                             const double *__restrict__ cs, double *__restrict__ y) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= m.nf) return;
+    const int K = S.K, nc = m.nc;
+    const double *xp = x + (size_t)k * m.nf;
+    const double *xr = x + (size_t)(K + 1) * m.nf;
+    const double *ph = S.phi + (size_t)k * m.nf;
+    const double xi = xp[i];
+    double v = 0.0;
+    for (int t = 0; t < m.wf; ++t) {
+        const int e = m.cf_edge[t * m.nf + i];
+        if (e < 0) break;
+        const int nb = m.cf_nb[t * m.nf + i];
+        v += m.etw[e] * rho_edge(m, S, k, e) * (xi - xp[nb]);
+        const double sgn = (m.eK[e] == i) ? 1.0 : -1.0;
+        const int rK = m.erK[e], rL = m.erL[e];
+        const double lam = m.elam[e];
+        const double wK = ptx_at(xr, cs, S.area, K, nc, k - 1, rK) + ptx_at(xr, cs, S.area, K, nc, k, rK);
+        const double wL = ptx_at(xr, cs, S.area, K, nc, k - 1, rL) + ptx_at(xr, cs, S.area, K, nc, k, rL);
+        v += 0.5 * sgn * m.elen[e] * grad_phi(m, ph, e) * (lam * wK + (1.0 - lam) * wL);
+    }
+    for (int t = 0; t < m.wo; ++t) {
+        const int c = m.fo_c[t * m.nf + i];
+        if (c < 0) break;
+        v += m.fo_w[t * m.nf + i] *
+             (ptx_at(xr, cs, S.area, K, nc, k - 1, c) - ptx_at(xr, cs, S.area, K, nc, k, c)) / S.dt;
+    }
+    y[(size_t)k * m.nf + i] = v;
+}
+
+// u^k = (B x_phi)^k - C (P^T x_rho)^k  (C = a' s / rho); with_c = 0 drops C.
+// (B x)^k = Omega^T (x^{k+1} - x^k)/dt + 1/2 sum R_T-weights (g^k grad x^k + g^{k+1} grad x^{k+1})
+// Writes u and per-block partial slice sums of u (for the projector P).
+__global__ void k_opB(MeshView m, StateView S, const double *__restrict__ xphi,
+                      const double *__restrict__ xr, const double *__restrict__ cs, int with_c,
+                      double *__restrict__ u, double *__restrict__ part) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double v = 0.0;
+    if (j < m.nc) {
+        const double *x0 = xphi + (size_t)k * m.nf, *x1 = x0 + m.nf;
+        const double *p0 = S.phi + (size_t)k * m.nf, *p1 = p0 + m.nf;
+        for (int t = 0; t < m.woc; ++t) {
+            const int f = m.co_f[t * m.nc + j];
+            if (f < 0) break;
+            v += m.co_w[t * m.nc + j] * (x1[f] - x0[f]) / S.dt;
+        }
+        double g = 0.0;
+        for (int t = 0; t < m.wr; ++t) {
+            const int e = m.cr_e[t * m.nc + j];
+            if (e < 0) break;
+            const int eK = m.eK[e], eL = m.eL[e];
+            const double id = m.einvd[e];
+            g += m.cr_w[t * m.nc + j] * ((p0[eK] - p0[eL]) * (x0[eK] - x0[eL]) +
+                                        (p1[eK] - p1[eL]) * (x1[eK] - x1[eL])) * id * id;
+        }
+        v += 0.5 * g;
+        const size_t q = (size_t)k * m.nc + j;
+        if (with_c) v -= m.ac[j] * S.s[q] / S.rho[q] * ptx_at(xr, cs, S.area, S.K, m.nc, k, j);
+        u[q] = v;
+    }
+    v = block_sum(v);
+    if (part && threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+// y_rho^k -= a' us[k] / area   (the projector P)
+template <typename T>
+__global__ void k_proj_fix(const double *__restrict__ ac, int nc, const double *__restrict__ us,
+                           double area, T *__restrict__ y) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j < nc) y[(size_t)k * nc + j] -= (T)(ac[j] * us[k] / area);
+}
+
+// y^k -= sums[k] * scale   (P^T or mean removal)
+template <typename T>
+__global__ void k_slice_shift(int n, const double *__restrict__ sums, double scale, T *__restrict__ y) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i < n) y[(size_t)k * n + i] -= (T)(sums[k] * scale);
+}
+
+// ------------------------------------------------------- vector utilities
+template <typename T>
+__global__ void k_fill(T *__restrict__ x, size_t n, T v) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) x[i] = v;
+}
+
+template <typename TO, typename TI>
+__global__ void k_convert(const TI *__restrict__ x, TO *__restrict__ y, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) y[i] = (TO)x[i];
+}
+
+// y = a x + b y
+template <typename T>
+__global__ void k_axpby(size_t n, double a, const T *__restrict__ x, double b, T *__restrict__ y) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+        y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+// partial sums of squares
+template <typename T>
+__global__ void k_nrm2_partial(size_t n, const T *__restrict__ x, double *__restrict__ part) {
+    double v = 0.0;
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        double xi = (double)x[i];
+        v += xi * xi;
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// Multi-dot for classical Gram-Schmidt: part[v * nblk + b] = sum over the
+// block's rows of V_v . w for the group of vectors v = g*8 .. g*8+7.
+template <typename T>
+__global__ void k_multidot(size_t n, const T *__restrict__ V, size_t ldv, int nv, const T *__restrict__ w,
+                           double *__restrict__ part) {
+    const int g0 = blockIdx.y * 8;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        const double wi = (double)w[i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (g0 + q < nv) acc[q] += (double)V[(size_t)(g0 + q) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (g0 + q >= nv) break;
+        double s = block_sum(acc[q]);
+        if (threadIdx.x == 0) part[(size_t)(g0 + q) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// w -= sum_v h[v] V_v, then partial sums of |w|^2 (h on device)
+template <typename T>
+__global__ void k_gs_update(size_t n, const T *__restrict__ V, size_t ldv, int nv, const double *__restrict__ h,
+                            T *__restrict__ w, double *__restrict__ part) {
+    double sq = 0.0;
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        double wi = (double)w[i];
+        for (int v = 0; v < nv; ++v) wi -= h[v] * (double)V[(size_t)v * ldv + i];
+        const T wt = (T)wi;
+        w[i] = wt;
+        sq += (double)wt * (double)wt;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.x] = sq;
+}
+
+// x += sum_v y[v] Z_v  (or x = ... when beta = 0)
+template <typename T, typename TX>
+__global__ void k_combine(size_t n, const T *__restrict__ Z, size_t ldz, int nv, const double *__restrict__ y,
+                          double beta, TX *__restrict__ x) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        double v = beta == 0.0 ? 0.0 : beta * (double)x[i];
+        for (int q = 0; q < nv; ++q) v += y[q] * (double)Z[(size_t)q * ldz + i];
+        x[i] = (TX)v;
+    }
+}
+
+// ------------------------------------------ preconditioner (type T) pieces
+// Per-linearisation coefficient arrays (type T):
+//   g[k][e]   gradient of the current phi at potential level k
+//   w0[k][e]  tw_e rho~^k_e   (level-0 multigrid edge weights)
+//   wc[k][ce] coarse edge weights of A~^k: len'/dist' (lam' rho_I + (1-lam') rho_J)
+template <typename T>
+__global__ void k_lin_edges(MeshView m, StateView S, T *__restrict__ g, T *__restrict__ w0) {
+    const int e = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (e >= m.ne) return;
+    const double *ph = S.phi + (size_t)k * m.nf;
+    g[(size_t)k * m.ne + e] = (T)grad_phi(m, ph, e);
+    w0[(size_t)k * m.ne + e] = (T)(m.etw[e] * rho_edge(m, S, k, e));
+}
+
+template <typename T>
+__global__ void k_lin_cedges(MeshView m, StateView S, T *__restrict__ wc) {
+    const int e = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (e >= m.nce) return;
+    const double *r = S.rho + (size_t)k * m.nc;
+    const double lam = m.celam[e];
+    wc[(size_t)k * m.nce + e] = (T)(m.cetw[e] * (lam * r[m.ceI[e]] + (1.0 - lam) * r[m.ceJ[e]]));
+}
+
+// Pseudo-Schur pass 1: u^k_i = (J (z^{k-1} + z^k)/2)_i = sum_c Omega_ic (..)_c / a_i
+template <typename T>
+__global__ void k_schur_lift(MeshView m, int K, const T *__restrict__ z, T *__restrict__ u) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= m.nf) return;
+    double v = 0.0;
+    for (int t = 0; t < m.wo; ++t) {
+        const int c = m.fo_c[t * m.nf + i];
+        if (c < 0) break;
+        double zz = 0.0;
+        if (k >= 1) zz += (double)z[(size_t)(k - 1) * m.nc + c];
+        if (k < K) zz += (double)z[(size_t)k * m.nc + c];
+        v += m.fo_w[t * m.nf + i] * 0.5 * zz;
+    }
+    u[(size_t)k * m.nf + i] = (T)(v / m.a[i]);
+}
+
+// Pseudo-Schur pass 2: v^k = M^-1 B~ z at potential level k:
+//   B~ z = Omega (z^k - z^{k-1})/dt + R_Tf[g^k * grad u^k]
+template <typename T>
+__global__ void k_schur_btilde(MeshView m, int K, double dt, const T *__restrict__ z, const T *__restrict__ u,
+                               const T *__restrict__ g, T *__restrict__ v) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= m.nf) return;
+    double acc = 0.0;
+    for (int t = 0; t < m.wo; ++t) {
+        const int c = m.fo_c[t * m.nf + i];
+        if (c < 0) break;
+        double dz = 0.0;
+        if (k < K) dz += (double)z[(size_t)k * m.nc + c];
+        if (k >= 1) dz -= (double)z[(size_t)(k - 1) * m.nc + c];
+        acc += m.fo_w[t * m.nf + i] * dz / dt;
+    }
+    const T *uk = u + (size_t)k * m.nf;
+    const T *gk = g + (size_t)k * m.ne;
+    const double ui = (double)uk[i];
+    for (int t = 0; t < m.wf; ++t) {
+        const int e = m.cf_edge[t * m.nf + i];
+        if (e < 0) break;
+        const int nb = m.cf_nb[t * m.nf + i];
+        const bool isK = m.eK[e] == i;
+        const double side = isK ? m.elam[e] : 1.0 - m.elam[e];
+        const double du = (isK ? 1.0 : -1.0) * (ui - (double)uk[nb]) * m.einvd[e];   // (u_K - u_L)/d
+        acc += side * m.eW[e] * (double)gk[e] * du;
+    }
+    v[(size_t)k * m.nf + i] = (T)(acc / m.a[i]);
+}
+
+// Pseudo-Schur pass 3: out^k = s (A~ z)^k - rho (B v)^k
+template <typename T>
+__global__ void k_schur_out(MeshView m, int K, double dt, const T *__restrict__ z, const T *__restrict__ v,
+                            const T *__restrict__ g, const T *__restrict__ wc, const T *__restrict__ rhoT,
+                            const T *__restrict__ sT, T *__restrict__ out) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= m.nc) return;
+    const size_t q = (size_t)k * m.nc + j;
+    const T *zk = z + (size_t)k * m.nc;
+    const T *wck = wc + (size_t)k * m.nce;
+    double at = 0.0;
+    const double zj = (double)zk[j];
+    for (int t = 0; t < m.wcc; ++t) {
+        const int e = m.cc_edge[t * m.nc + j];
+        if (e < 0) break;
+        at += (double)wck[e] * (zj - (double)zk[m.cc_nb[t * m.nc + j]]);
+    }
+    const T *v0 = v + (size_t)k * m.nf, *v1 = v0 + m.nf;
+    const T *g0 = g + (size_t)k * m.ne, *g1 = g0 + m.ne;
+    double b = 0.0;
+    for (int t = 0; t < m.woc; ++t) {
+        const int f = m.co_f[t * m.nc + j];
+        if (f < 0) break;
+        b += m.co_w[t * m.nc + j] * ((double)v1[f] - (double)v0[f]) / dt;
+    }
+    double gg = 0.0;
+    for (int t = 0; t < m.wr; ++t) {
+        const int e = m.cr_e[t * m.nc + j];
+        if (e < 0) break;
+        const int eK = m.eK[e], eL = m.eL[e];
+        gg += m.cr_w[t * m.nc + j] * m.einvd[e] *
+              ((double)g0[e] * ((double)v0[eK] - (double)v0[eL]) + (double)g1[e] * ((double)v1[eK] - (double)v1[eL]));
+    }
+    b += 0.5 * gg;
+    out[q] = (T)((double)sT[q] * at - (double)rhoT[q] * b);
+}
+
+// probe vector: 1 at (k, j) with k % 3 == tc and color[j] == c
+template <typename T>
+__global__ void k_probe(int nc, const int *__restrict__ color, int tc, int c, T *__restrict__ p) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j < nc) p[(size_t)k * nc + j] = (T)((k % 3 == tc && color[j] == c) ? 1.0 : 0.0);
+}
+
+// scatter a probe response into the three diagonals of the time-line blocks
+template <typename T>
+__global__ void k_probe_scatter(int nc, int K, const int *__restrict__ color, int tc, int c,
+                                const T *__restrict__ r, double *__restrict__ d0, double *__restrict__ dl,
+                                double *__restrict__ du) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= nc || color[j] != c) return;
+    const size_t q = (size_t)k * nc + j;
+    const double val = (double)r[q];
+    if (k % 3 == tc) d0[q] = val;
+    else if (k >= 1 && (k - 1) % 3 == tc) dl[q] = val;
+    else if (k + 1 < K && (k + 1) % 3 == tc) du[q] = val;
+}
+
+// Thomas factorisation along time for every coarse cell: inv_dd[k] and
+// multipliers l[k] = dl[k] / dd[k-1]; weak pivots fall back to the diagonal.
+template <typename T>
+__global__ void k_tri_factor(int nc, int K, const double *__restrict__ d0, const double *__restrict__ dl,
+                             const double *__restrict__ du, T *__restrict__ inv_dd, T *__restrict__ lm,
+                             T *__restrict__ up) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= nc) return;
+    double prev = 0.0, prev_up = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const size_t q = (size_t)k * nc + j;
+        double d = d0[q], l = 0.0;
+        if (k > 0 && prev != 0.0) {
+            l = dl[q] / prev;
+            double dd = d - l * prev_up;
+            if (!(fabs(dd) > 1e-3 * fabs(d)) || !isfinite(dd)) { l = 0.0; dd = d; }
+            d = dd;
+        }
+        if (!(fabs(d) > 0.0) || !isfinite(d)) d = 1.0;
+        inv_dd[q] = (T)(1.0 / d);
+        lm[q] = (T)l;
+        const double u = (k + 1 < K) ? du[q] : 0.0;
+        up[q] = (T)u;
+        prev = d;
+        prev_up = u;
+    }
+}
+
+template <typename T>
+__global__ void k_tri_solve(int nc, int K, const T *__restrict__ inv_dd, const T *__restrict__ lm,
+                            const T *__restrict__ up, const T *__restrict__ r, T *__restrict__ x) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= nc) return;
+    double y = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const size_t q = (size_t)k * nc + j;
+        y = (double)r[q] - (double)lm[q] * y;
+        x[q] = (T)y;
+    }
+    double xn = 0.0;
+    for (int k = K - 1; k >= 0; --k) {
+        const size_t q = (size_t)k * nc + j;
+        xn = ((double)x[q] - (double)up[q] * xn) * (double)inv_dd[q];
+        x[q] = (T)xn;
+    }
+}
+
+// rhs of the pseudo-Schur system: -rho (P d)^k, dsum[k] = 1^T d^k
+template <typename T>
+__global__ void k_schur_rhs(const double *__restrict__ ac, int nc, double area, const double *__restrict__ dsum,
+                            const T *__restrict__ rhoT, const T *__restrict__ d, T *__restrict__ out) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= nc) return;
+    const size_t q = (size_t)k * nc + j;
+    out[q] = (T)(-(double)rhoT[q] * ((double)d[q] - ac[j] * dsum[k] / area));
+}
+
+// y^k = M'^-1 A~^k z^k  (before P^T)
+template <typename T>
+__global__ void k_coarse_lap_scaled(MeshView m, const T *__restrict__ z, const T *__restrict__ wc,
+                                    T *__restrict__ y) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= m.nc) return;
+    const T *zk = z + (size_t)k * m.nc;
+    const T *wck = wc + (size_t)k * m.nce;
+    const double zj = (double)zk[j];
+    double at = 0.0;
+    for (int t = 0; t < m.wcc; ++t) {
+        const int e = m.cc_edge[t * m.nc + j];
+        if (e < 0) break;
+        at += (double)wck[e] * (zj - (double)zk[m.cc_nb[t * m.nc + j]]);
+    }
+    y[(size_t)k * m.nc + j] = (T)(at / m.ac[j]);
+}
+
+// b^k = c^k - (B^T y)^k (type T, y already projected)
+template <typename T>
+__global__ void k_bt_rhs(MeshView m, int K, double dt, const T *__restrict__ c, const T *__restrict__ y,
+                         const T *__restrict__ g, T *__restrict__ b) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= m.nf) return;
+    auto yat = [&](int l, int cc) -> double { return (l >= 0 && l < K) ? (double)y[(size_t)l * m.nc + cc] : 0.0; };
+    double v = 0.0;
+    for (int t = 0; t < m.wo; ++t) {
+        const int cc = m.fo_c[t * m.nf + i];
+        if (cc < 0) break;
+        v += m.fo_w[t * m.nf + i] * (yat(k - 1, cc) - yat(k, cc)) / dt;
+    }
+    const T *gk = g + (size_t)k * m.ne;
+    for (int t = 0; t < m.wf; ++t) {
+        const int e = m.cf_edge[t * m.nf + i];
+        if (e < 0) break;
+        const double sgn = (m.eK[e] == i) ? 1.0 : -1.0;
+        const int rK = m.erK[e], rL = m.erL[e];
+        const double lam = m.elam[e];
+        const double re = lam * (yat(k - 1, rK) + yat(k, rK)) + (1.0 - lam) * (yat(k - 1, rL) + yat(k, rL));
+        v += 0.5 * sgn * m.elen[e] * (double)gk[e] * re;
+    }
+    const size_t q = (size_t)k * m.nf + i;
+    b[q] = (T)((double)c[q] - v);
+}
+
+// ------------------------------------------------------------- multigrid
+// Graph Laplacian of one level, all slices: (A x)_i = sum_t w_e (x_i - x_nb)
+struct LevelView {
+    int n, w, ne;
+    const int *nb, *ed;
+};
+
+// Galerkin edge weights of the next level: wn[k][c] = sum over member edges
+template <typename T>
+__global__ void k_mg_coarse_w(int ne_next, int ne, const int *__restrict__ ptr, const int *__restrict__ idx,
+                              const T *__restrict__ w, T *__restrict__ wn) {
+    const int c = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (c >= ne_next) return;
+    double v = 0.0;
+    for (int p = ptr[c]; p < ptr[c + 1]; ++p) v += (double)w[(size_t)k * ne + idx[p]];
+    wn[(size_t)k * ne_next + c] = (T)v;
+}
+
+template <typename T>
+__global__ void k_mg_diag(LevelView L, const T *__restrict__ w, T *__restrict__ dinv) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= L.n) return;
+    double d = 0.0;
+    for (int t = 0; t < L.w; ++t) {
+        const int e = L.ed[t * L.n + i];
+        if (e < 0) break;
+        d += (double)w[(size_t)k * L.ne + e];
+    }
+    dinv[(size_t)k * L.n + i] = (T)(d > 0.0 ? 1.0 / d : 0.0);
+}
+
+template <typename T>
+__device__ __forceinline__ double lap_row(const LevelView &L, const T *w, const T *x, int i) {
+    const double xi = (double)x[i];
+    double v = 0.0;
+    for (int t = 0; t < L.w; ++t) {
+        const int e = L.ed[t * L.n + i];
+        if (e < 0) break;
+        v += (double)w[e] * (xi - (double)x[L.nb[t * L.n + i]]);
+    }
+    return v;
+}
+
+template <typename T>
+__global__ void k_mg_apply(LevelView L, const T *__restrict__ w, const T *__restrict__ x, T *__restrict__ y) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= L.n) return;
+    y[(size_t)k * L.n + i] = (T)lap_row(L, w + (size_t)k * L.ne, x + (size_t)k * L.n, i);
+}
+
+// Chebyshev smoothing of D^-1 A on [lo, hi] (Saad, Alg. 12.1):
+// init: r = D^-1 (b - A x) (x = 0 when zero_x), d = r / theta
+template <typename T>
+__global__ void k_cheb_init(LevelView L, const T *__restrict__ w, const T *__restrict__ dinv,
+                            const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
+                            double theta, int zero_x) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= L.n) return;
+    const size_t q = (size_t)k * L.n + i;
+    double ax = 0.0;
+    if (zero_x) x[q] = (T)0;
+    else ax = lap_row(L, w + (size_t)k * L.ne, x + (size_t)k * L.n, i);
+    const double rr = ((double)b[q] - ax) * (double)dinv[q];
+    r[q] = (T)rr;
+    d[q] = (T)(rr / theta);
+}
+
+// step: x += d; r -= D^-1 A d; d' = c1 d + c2 r
+template <typename T>
+__global__ void k_cheb_step(LevelView L, const T *__restrict__ w, const T *__restrict__ dinv, T *__restrict__ x,
+                            T *__restrict__ r, const T *__restrict__ d, T *__restrict__ dn, double c1, double c2) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= L.n) return;
+    const size_t q = (size_t)k * L.n + i;
+    const double ad = lap_row(L, w + (size_t)k * L.ne, d + (size_t)k * L.n, i);
+    const double di = (double)d[q];
+    x[q] = (T)((double)x[q] + di);
+    const double rn = (double)r[q] - ad * (double)dinv[q];
+    r[q] = (T)rn;
+    dn[q] = (T)(c1 * di + c2 * rn);
+}
+
+// restriction of the residual: bc[c] = sum_{i in agg c} (b - A x)_i
+template <typename T>
+__global__ void k_mg_restrict(LevelView L, int n_next, const int *__restrict__ ptr, const int *__restrict__ idx,
+                              const T *__restrict__ w, const T *__restrict__ b, const T *__restrict__ x,
+                              T *__restrict__ bc) {
+    const int c = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (c >= n_next) return;
+    const T *wk = w + (size_t)k * L.ne;
+    const T *xk = x + (size_t)k * L.n;
+    const T *bk = b + (size_t)k * L.n;
+    double v = 0.0;
+    for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
+        const int i = idx[p];
+        v += (double)bk[i] - lap_row(L, wk, xk, i);
+    }
+    bc[(size_t)k * n_next + c] = (T)v;
+}
+
+template <typename T>
+__global__ void k_mg_prolong(int n, int n_next, const int *__restrict__ agg, const T *__restrict__ xc,
+                             T *__restrict__ x) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= n) return;
+    const size_t q = (size_t)k * n + i;
+    x[q] = (T)((double)x[q] + (double)xc[(size_t)k * n_next + agg[i]]);
+}
+
+// per-slice PCG updates with host-provided per-slice scalars in alpha/beta
+template <typename T>
+__global__ void k_pcg_xr(int n, const double *__restrict__ alpha, const T *__restrict__ p, const T *__restrict__ q,
+                         T *__restrict__ x, T *__restrict__ r) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= n) return;
+    const size_t o = (size_t)k * n + i;
+    const double a = alpha[k];
+    x[o] = (T)((double)x[o] + a * (double)p[o]);
+    r[o] = (T)((double)r[o] - a * (double)q[o]);
+}
+
+template <typename T>
+__global__ void k_pcg_p(int n, const double *__restrict__ beta, const T *__restrict__ z, T *__restrict__ p) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= n) return;
+    const size_t o = (size_t)k * n + i;
+    p[o] = (T)((double)z[o] + beta[k] * (double)p[o]);
+}
+
+// ----------------------------------------------------- Newton step pieces
+// Newton right-hand side of the projected system: f = -F_phi (copied),
+// g~ = -F_rho + a' (F_s) / rho, written as (f; g~) in out; P applied later.
+__global__ void k_newton_rhs(MeshView m, StateView S, const double *__restrict__ F, double *__restrict__ out,
+                             double *__restrict__ gt, double *__restrict__ part, size_t nphi, size_t mrho) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double v = 0.0;
+    if (j < m.nc) {
+        const size_t q = (size_t)k * m.nc + j;
+        const double g = -F[nphi + q], h = -F[nphi + mrho + q];
+        v = g - m.ac[j] * h / S.rho[q];
+        gt[q] = v;
+        out[nphi + q] = v;
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+__global__ void k_neg_copy(size_t n, const double *__restrict__ x, double *__restrict__ y) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) y[i] = -x[i];
+}
+
+// recovery residual r = g~ - B dphi_bar + C drho (B dphi_bar in bphi), partial slice sums
+__global__ void k_recover_r(int nc, const double *__restrict__ ac, const double *__restrict__ gt,
+                            const double *__restrict__ bphi, const double *__restrict__ drho, StateView S,
+                            double *__restrict__ part) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double v = 0.0;
+    if (j < nc) {
+        const size_t q = (size_t)k * nc + j;
+        v = gt[q] - bphi[q] + ac[j] * S.s[q] / S.rho[q] * drho[q];
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+// dphi^k += shift[k]
+__global__ void k_add_shift(int nf, const double *__restrict__ shift, double *__restrict__ dphi) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i < nf) dphi[(size_t)k * nf + i] += shift[k];
+}
+
+// ds = (h - s drho)/rho with h = -(rho s - mu); partial min of the step ratios
+__global__ void k_ds_ratio(size_t n, StateView S, double mu, const double *__restrict__ drho,
+                           double *__restrict__ ds, double *__restrict__ part) {
+    double am = DBL_MAX;
+    for (size_t q = (size_t)blockIdx.x * BS + threadIdx.x; q < n; q += (size_t)gridDim.x * BS) {
+        const double r = S.rho[q], s = S.s[q], dr = drho[q];
+        const double h = -(r * s - mu);
+        const double d = (h - s * dr) / r;
+        ds[q] = d;
+        if (dr < 0) am = fmin(am, -r / dr);
+        if (d < 0) am = fmin(am, -s / d);
+    }
+    am = block_min(am);
+    if (threadIdx.x == 0) part[blockIdx.x] = am;
+}
+
+// x += alpha dx
+__global__ void k_axpy(size_t n, double a, const double *__restrict__ dx, double *__restrict__ x) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) x[i] += a * dx[i];
+}
+
+// rho^k *= m0 / mass[k]
+__global__ void k_renorm(int nc, const double *__restrict__ mass, double m0, double *__restrict__ rho) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j < nc) rho[(size_t)k * nc + j] *= m0 / mass[k];
+}
+
+// ------------------------------------------------------------- outputs
+// partial sums of W rho~ g^2 over edges and potential levels
+__global__ void k_ke_partial(MeshView m, StateView S, double *__restrict__ part) {
+    const int e = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double v = 0.0;
+    if (e < m.ne) {
+        const double g = grad_phi(m, S.phi + (size_t)k * m.nf, e);
+        v = m.eW[e] * rho_edge(m, S, k, e) * g * g;
+    }
+    v = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+// envelope parts per coarse cell: R_T (g^2) at the first and last potential
+// levels and Omega^T phi there.  Writes 4 arrays of nc.
+__global__ void k_boundary_terms(MeshView m, StateView S, const double *__restrict__ phi_first,
+                                 const double *__restrict__ phi_last, double *__restrict__ om_first,
+                                 double *__restrict__ om_last, double *__restrict__ rt_first,
+                                 double *__restrict__ rt_last) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= m.nc) return;
+    double o1 = 0.0, o2 = 0.0, r1 = 0.0, r2 = 0.0;
+    for (int t = 0; t < m.woc; ++t) {
+        const int f = m.co_f[t * m.nc + j];
+        if (f < 0) break;
+        o1 += m.co_w[t * m.nc + j] * phi_first[f];
+        o2 += m.co_w[t * m.nc + j] * phi_last[f];
+    }
+    for (int t = 0; t < m.wr; ++t) {
+        const int e = m.cr_e[t * m.nc + j];
+        if (e < 0) break;
+        const double g1 = grad_phi(m, phi_first, e), g2 = grad_phi(m, phi_last, e);
+        r1 += m.cr_w[t * m.nc + j] * g1 * g1;
+        r2 += m.cr_w[t * m.nc + j] * g2 * g2;
+    }
+    om_first[j] = o1; om_last[j] = o2; rt_first[j] = r1; rt_last[j] = r2;
+}
+
+// adjoint corrections: out[j] = sgn_t Omega^T q / dt + 1/2 R_T(g * grad q) at one level
+__global__ void k_adjoint_corr(MeshView m, const double *__restrict__ ph, const double *__restrict__ q,
+                               double tsign, double dt, double *__restrict__ out) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= m.nc) return;
+    double v = 0.0;
+    for (int t = 0; t < m.woc; ++t) {
+        const int f = m.co_f[t * m.nc + j];
+        if (f < 0) break;
+        v += tsign * m.co_w[t * m.nc + j] * q[f] / dt;
+    }
+    double gg = 0.0;
+    for (int t = 0; t < m.wr; ++t) {
+        const int e = m.cr_e[t * m.nc + j];
+        if (e < 0) break;
+        gg += m.cr_w[t * m.nc + j] * grad_phi(m, ph, e) * grad_phi(m, q, e);
+    }
+    out[j] = v + 0.5 * gg;
+}
+
+}  // namespace kern
+}  // namespace otbb

@@ -1,0 +1,1294 @@
+// Interior-point solver: state, operators, BB preconditioner, FGMRES,
+// Newton step, continuation, outputs, gradient, and the C ABI.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mesh.hpp"
+
+using namespace otbb;
+using namespace otbb::kern;
+
+namespace otbb {
+
+static thread_local std::string g_last_error = "no error";
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+static inline dim3 grid2(int n, int nseg) { return dim3((unsigned)std::max(1, ceil_div(n, BS)), (unsigned)nseg); }
+static inline int grid1(size_t n, int cap = 1024) {
+    return (int)std::max<size_t>(1, std::min<size_t>((n + BS - 1) / BS, (size_t)cap));
+}
+
+MeshView mesh_view(const ot_mesh *m) {
+    const MeshHost &h = m->h;
+    MeshView v;
+    v.nf = h.nf; v.nc = h.nc; v.ne = h.ne; v.nce = h.nce;
+    v.wf = h.wf; v.wo = h.wo; v.woc = h.woc; v.wr = h.wr; v.wcc = h.wcc;
+    v.a = m->a; v.ac = m->ac; v.elam = m->elam; v.etw = m->etw; v.eW = m->eW; v.einvd = m->einvd;
+    v.elen = m->elen; v.cetw = m->cetw; v.celam = m->celam; v.fo_w = m->fo_w; v.co_w = m->co_w; v.cr_w = m->cr_w;
+    v.eK = m->eK; v.eL = m->eL; v.erK = m->erK; v.erL = m->erL; v.ceI = m->ceI; v.ceJ = m->ceJ;
+    v.cf_edge = m->cf_edge; v.cf_nb = m->cf_nb; v.fo_c = m->fo_c; v.co_f = m->co_f; v.cr_e = m->cr_e;
+    v.cc_edge = m->cc_edge; v.cc_nb = m->cc_nb;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Reduction scratch bound to a stream
+// ---------------------------------------------------------------------------
+struct Reducer {
+    hipStream_t s = nullptr;
+    DBuf<double> part, dev;
+    double *host = nullptr;      // pinned
+    size_t host_n = 0;
+    void init(size_t npart, size_t ndev, hipStream_t st) {
+        s = st;
+        part.alloc(npart);
+        dev.alloc(ndev);
+        host_n = ndev;
+        OT_HIP(hipHostMalloc((void **)&host, ndev * sizeof(double), hipHostMallocDefault));
+    }
+    ~Reducer() { if (host) (void)hipHostFree(host); }
+    // copy n device scalars to host and wait
+    const double *fetch(const double *d, size_t n) {
+        OT_REQUIRE(n <= host_n, OT_EINVAL, "internal: reduction fetch too large");
+        OT_HIP(hipGetLastError());
+        OT_HIP(hipMemcpyAsync(host, d, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+        return host;
+    }
+    // final reduction of nseg segments of nblk partials into dev[off..]
+    double *seg_final(int nseg, int nblk, size_t off = 0) {
+        k_seg_final<<<nseg, BS, 0, s>>>(part, nblk, dev.p + off);
+        return dev.p + off;
+    }
+};
+
+}  // namespace otbb
+
+// ---------------------------------------------------------------------------
+// State
+// ---------------------------------------------------------------------------
+struct PrecBase {
+    virtual ~PrecBase() = default;
+    virtual void setup(ot_state *st) = 0;
+    virtual void apply(ot_state *st, const double *r, double *z) = 0;
+    // component access for the inspection entry points (FP64 device in/out)
+    virtual void schur_apply_d(ot_state *st, const double *z, double *out) = 0;
+    virtual int schur_solve_d(ot_state *st, const double *rhs, double *z, double tol, int maxit) = 0;
+    virtual void tri_diagonals_d(ot_state *st, double *d0, double *dl, double *du) = 0;
+    virtual int laplace_solve_d(ot_state *st, const double *b, double *x, double tol, int maxit) = 0;
+    virtual void vcycle_d(ot_state *st, const double *b, double *x) = 0;
+    virtual size_t level_data_d(ot_state *st, int level, int what, double *out) = 0;
+};
+
+struct ot_state {
+    const ot_mesh *mesh = nullptr;
+    int K = 0;
+    ot_options opt;
+    hipStream_t stream = nullptr;
+    size_t nphi = 0, mrho = 0, N = 0;
+    double mu = 1.0, m0 = 0.0, dt = 0.0, area = 0.0;
+    DBuf<double> phi, rho, s, rin, rf;
+    DBuf<double> F, rhs, sol, gt, tmpN, tmpr, ds, sums, shift;
+    DBuf<double> V, Z;
+    Reducer red;
+    std::unique_ptr<PrecBase> prec;
+    int prec_kind = -1;
+    bool lin_valid = false;
+    ot_stats acc{};
+    // last FGMRES info
+    int last_iters = 0;
+    double last_relres = 0.0;
+    bool last_converged = false;
+
+    StateView view() const {
+        StateView v;
+        v.K = K; v.dt = dt; v.area = area;
+        v.phi = phi; v.rho = rho; v.s = s; v.rin = rin; v.rf = rf;
+        return v;
+    }
+};
+
+namespace otbb {
+
+// slice sums sums[k] = sum_i w_i x[k n + i] on device (nseg slices)
+template <typename T>
+static double *slice_sums(ot_state *st, const T *x, const double *w, int n, int nseg, double *out) {
+    int nblk = std::min(256, std::max(1, ceil_div(n, BS)));
+    k_seg_partial<T><<<dim3(nblk, nseg), BS, 0, st->stream>>>(x, w, n, st->red.part);
+    k_seg_final<<<nseg, BS, 0, st->stream>>>(st->red.part, nblk, out);
+    return out;
+}
+
+template <typename T>
+static double *slice_dots(ot_state *st, const T *x, const T *y, int n, int nseg, double *out) {
+    int nblk = std::min(256, std::max(1, ceil_div(n, BS)));
+    k_seg_dot_partial<T><<<dim3(nblk, nseg), BS, 0, st->stream>>>(x, y, n, st->red.part);
+    k_seg_final<<<nseg, BS, 0, st->stream>>>(st->red.part, nblk, out);
+    return out;
+}
+
+template <typename T>
+static double norm2(ot_state *st, const T *x, size_t n) {
+    int nblk = grid1(n);
+    k_nrm2_partial<T><<<nblk, BS, 0, st->stream>>>(n, x, st->red.part);
+    double *d = st->red.seg_final(1, nblk);
+    return std::sqrt(st->red.fetch(d, 1)[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Residual and saddle operator (FP64)
+// ---------------------------------------------------------------------------
+static double residual(ot_state *st) {
+    const ot_mesh *m = st->mesh;
+    MeshView mv = mesh_view(m);
+    StateView sv = st->view();
+    dim3 gf = grid2(m->h.nf, st->K + 1), gc = grid2(m->h.nc, st->K);
+    k_res_phi<<<gf, BS, 0, st->stream>>>(mv, sv, st->F, st->red.part);
+    int n1 = gf.x * gf.y;
+    k_res_rho<<<gc, BS, 0, st->stream>>>(mv, sv, st->mu, st->F.p + st->nphi, st->F.p + st->nphi + st->mrho,
+                                         st->red.part.p + n1);
+    int n2 = gc.x * gc.y;
+    double *d = st->red.seg_final(1, n1 + n2);
+    return std::sqrt(st->red.fetch(d, 1)[0]);
+}
+
+// y = J_P x (both length N, device)
+static void apply_saddle(ot_state *st, const double *x, double *y) {
+    const ot_mesh *m = st->mesh;
+    MeshView mv = mesh_view(m);
+    StateView sv = st->view();
+    const int K = st->K, nf = m->h.nf, nc = m->h.nc;
+    double *cs = st->sums.p;                 // a'^T x_rho^k
+    double *us = st->sums.p + K + 2;         // 1^T u^k
+    slice_sums<double>(st, x + st->nphi, m->ac, nc, K, cs);
+    k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mv, sv, x, cs, y);
+    dim3 gc = grid2(nc, K);
+    k_opB<<<gc, BS, 0, st->stream>>>(mv, sv, x, x + st->nphi, cs, 1, y + st->nphi, st->red.part);
+    k_seg_final<<<K, BS, 0, st->stream>>>(st->red.part, gc.x, us);
+    k_proj_fix<double><<<gc, BS, 0, st->stream>>>(m->ac, nc, us, st->area, y + st->nphi);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov helpers
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt with one reorthogonalisation of w against the nv
+// vectors of V (leading dimension ld).  h[0..nv) receives the coefficients,
+// the return value is |w| after orthogonalisation.  One host sync.
+template <typename T>
+static double cgs2(ot_state *st, const T *V, size_t ld, int nv, T *w, size_t n, double *h) {
+    Reducer &R = st->red;
+    const int nblk = grid1(n, 512);
+    const int ng = (nv + 7) / 8;
+    double *h1 = R.dev.p, *h2 = R.dev.p + 64, *nr = R.dev.p + 128;
+    for (int pass = 0; pass < 2; ++pass) {
+        double *hp = pass ? h2 : h1;
+        k_multidot<T><<<dim3(nblk, ng), BS, 0, st->stream>>>(n, V, ld, nv, w, R.part);
+        k_seg_final<<<nv, BS, 0, st->stream>>>(R.part, nblk, hp);
+        k_gs_update<T><<<nblk, BS, 0, st->stream>>>(n, V, ld, nv, hp, w, R.part);
+    }
+    k_seg_final<<<1, BS, 0, st->stream>>>(R.part, nblk, nr);
+    const double *hh = R.fetch(R.dev.p, 129);
+    for (int i = 0; i < nv; ++i) h[i] = hh[i] + hh[64 + i];
+    return std::sqrt(std::max(hh[128], 0.0));
+}
+
+// Givens-rotation least squares state for (F)GMRES
+struct Givens {
+    int m;
+    std::vector<double> H, cs, sn, g;
+    explicit Givens(int m_) : m(m_), H((size_t)(m_ + 1) * m_, 0.0), cs(m_), sn(m_), g(m_ + 1, 0.0) {}
+    double &h(int i, int j) { return H[(size_t)j * (m + 1) + i]; }
+    void reset(double beta) { std::fill(g.begin(), g.end(), 0.0); g[0] = beta; }
+    // column j holds h(0..j+1, j); returns |residual|
+    double push(int j) {
+        for (int i = 0; i < j; ++i) {
+            double a = h(i, j), b = h(i + 1, j);
+            h(i, j) = cs[i] * a + sn[i] * b;
+            h(i + 1, j) = -sn[i] * a + cs[i] * b;
+        }
+        double a = h(j, j), b = h(j + 1, j);
+        double r = std::hypot(a, b);
+        cs[j] = r > 0 ? a / r : 1.0;
+        sn[j] = r > 0 ? b / r : 0.0;
+        h(j, j) = r;
+        h(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        return std::fabs(g[j + 1]);
+    }
+    std::vector<double> solve(int k) {      // k columns
+        std::vector<double> y(k, 0.0);
+        for (int i = k - 1; i >= 0; --i) {
+            double v = g[i];
+            for (int q = i + 1; q < k; ++q) v -= h(i, q) * y[q];
+            y[i] = h(i, i) != 0.0 ? v / h(i, i) : 0.0;
+        }
+        return y;
+    }
+};
+
+}  // namespace otbb
+
+// ---------------------------------------------------------------------------
+// BB preconditioner, templated on the arithmetic type of its kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+struct BBPrec : PrecBase {
+    int nf = 0, nc = 0, ne = 0, nce = 0, K = 0, nlev = 0;
+    size_t nphi = 0, mrho = 0;
+    DBuf<T> g, wc, rhoT, sT;
+    std::vector<DBuf<T>> lw, ldinv;            // per level edge weights / inverse diagonal
+    std::vector<DBuf<T>> lb, lx, lr, ld, ld2;  // per level work (level >= 1 use lb/lx)
+    DBuf<double> d0, dl, du;
+    DBuf<T> inv_dd, lm, up;
+    DBuf<T> cT, dT, rhsS, zS, yT, bT, uT, vT, tmpm, tmpm2, probe;
+    DBuf<T> VS;                                // inner GMRES basis
+    DBuf<T> px, pr, pz, pp, pq;                // PCG work
+    DBuf<double> coef;                         // per-slice alpha / beta
+    int mS = 20;
+    const double hi = 2.0, lo_ratio = 0.3, coarse_lo_ratio = 0.02;
+    int nu = 2, coarse_deg = 8;
+
+    void alloc(ot_state *st) {
+        const ot_mesh *m = st->mesh;
+        nf = m->h.nf; nc = m->h.nc; ne = m->h.ne; nce = m->h.nce; K = st->K;
+        nphi = st->nphi; mrho = st->mrho;
+        nlev = (int)m->lv.size();
+        mS = std::max(2, st->opt.inner_restart);
+        g.alloc((size_t)(K + 1) * std::max(ne, 1));
+        wc.alloc((size_t)K * std::max(nce, 1));
+        rhoT.alloc(mrho); sT.alloc(mrho);
+        lw.clear(); ldinv.clear(); lb.clear(); lx.clear(); lr.clear(); ld.clear(); ld2.clear();
+        for (int l = 0; l < nlev; ++l) {
+            const MGLevelDev &L = m->lv[l];
+            lw.emplace_back((size_t)(K + 1) * std::max(L.ne, 1));
+            ldinv.emplace_back((size_t)(K + 1) * L.n);
+            lb.emplace_back((size_t)(K + 1) * L.n);
+            lx.emplace_back((size_t)(K + 1) * L.n);
+            lr.emplace_back((size_t)(K + 1) * L.n);
+            ld.emplace_back((size_t)(K + 1) * L.n);
+            ld2.emplace_back((size_t)(K + 1) * L.n);
+        }
+        d0.alloc(mrho); dl.alloc(mrho); du.alloc(mrho);
+        inv_dd.alloc(mrho); lm.alloc(mrho); up.alloc(mrho);
+        cT.alloc(nphi); dT.alloc(mrho); rhsS.alloc(mrho); zS.alloc(mrho); yT.alloc(mrho);
+        bT.alloc(nphi); uT.alloc(nphi); vT.alloc(nphi); tmpm.alloc(mrho); tmpm2.alloc(mrho); probe.alloc(mrho);
+        VS.alloc((size_t)(mS + 1) * mrho);
+        px.alloc(nphi); pr.alloc(nphi); pz.alloc(nphi); pp.alloc(nphi); pq.alloc(nphi);
+        coef.alloc(2 * (K + 2));
+    }
+
+    LevelView lview(const ot_mesh *m, int l) const {
+        const MGLevelDev &L = m->lv[l];
+        LevelView v;
+        v.n = L.n; v.w = L.w; v.ne = L.ne; v.nb = L.nb; v.ed = L.ed;
+        return v;
+    }
+
+    // linearisation: FP32/FP64 copies of the coefficients, multigrid
+    // hierarchy weights, probed time-line tridiagonal factors
+    void setup(ot_state *st) override {
+        if (nf == 0) alloc(st);
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        StateView sv = st->view();
+        k_lin_edges<T><<<grid2(ne, K + 1), BS, 0, s>>>(mv, sv, g, lw[0]);
+        if (nce > 0) k_lin_cedges<T><<<grid2(nce, K), BS, 0, s>>>(mv, sv, wc);
+        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->rho, rhoT, mrho);
+        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->s, sT, mrho);
+        for (int l = 0; l < nlev; ++l) {
+            const MGLevelDev &L = m->lv[l];
+            if (l > 0) {
+                const MGLevelDev &P = m->lv[l - 1];
+                k_mg_coarse_w<T><<<grid2(P.ne_next, K + 1), BS, 0, s>>>(P.ne_next, P.ne, P.cedge_ptr,
+                                                                         P.cedge_idx, lw[l - 1], lw[l]);
+            }
+            k_mg_diag<T><<<grid2(L.n, K + 1), BS, 0, s>>>(lview(m, l), lw[l], ldinv[l]);
+        }
+        // probe the block-tridiagonal pseudo-Schur operator for its three
+        // time diagonals at every coarse cell
+        const int ncol = m->h.ncolor;
+        dim3 gc = grid2(nc, K);
+        k_fill<double><<<grid1(mrho), BS, 0, s>>>(dl, mrho, 0.0);
+        k_fill<double><<<grid1(mrho), BS, 0, s>>>(du, mrho, 0.0);
+        for (int tc = 0; tc < std::min(3, K); ++tc)
+            for (int c = 0; c < ncol; ++c) {
+                k_probe<T><<<gc, BS, 0, s>>>(nc, m->color, tc, c, probe);
+                schur_apply(st, probe, tmpm);
+                k_probe_scatter<T><<<gc, BS, 0, s>>>(nc, K, m->color, tc, c, tmpm, d0, dl, du);
+            }
+        k_tri_factor<T><<<grid1(nc, 1 << 20), BS, 0, s>>>(nc, K, d0, dl, du, inv_dd, lm, up);
+    }
+
+    // out = (Diag(s) A~ - Diag(rho) B M^-1 B~) z
+    void schur_apply(ot_state *st, const T *z, T *out) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, z, uT);
+        k_schur_btilde<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, st->dt, z, uT, g, vT);
+        k_schur_out<T><<<grid2(nc, K), BS, 0, s>>>(mv, K, st->dt, z, vT, g, wc, rhoT, sT, out);
+    }
+
+    void tri_apply(ot_state *st, const T *r, T *x) {
+        k_tri_solve<T><<<grid1(nc, 1 << 20), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, r, x);
+    }
+
+    // right-preconditioned restarted GMRES on the pseudo-Schur system; w = 0 start
+    int gmres_schur(ot_state *st, const T *rhs, T *w, double tol, int maxit) {
+        hipStream_t s = st->stream;
+        const size_t n = mrho;
+        k_fill<T><<<grid1(n), BS, 0, s>>>(w, n, (T)0);
+        double beta = norm2<T>(st, rhs, n);
+        if (beta == 0.0) return 0;
+        const double target = tol * beta;
+        Givens G(mS);
+        int its = 0;
+        // r = rhs (w = 0)
+        k_convert<T, T><<<grid1(n), BS, 0, s>>>(rhs, VS.p, n);
+        double res = beta;
+        while (its < maxit) {
+            k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 0.0, VS.p, 1.0 / beta, VS.p);
+            G.reset(beta);
+            int j = 0;
+            std::vector<double> h(mS + 1);
+            for (; j < mS && its < maxit; ++j) {
+                tri_apply(st, VS.p + (size_t)j * n, tmpm);
+                T *wn = VS.p + (size_t)(j + 1) * n;
+                schur_apply(st, tmpm, wn);
+                double hn = cgs2<T>(st, VS.p, n, j + 1, wn, n, h.data());
+                for (int i = 0; i <= j; ++i) G.h(i, j) = h[i];
+                G.h(j + 1, j) = hn;
+                ++its;
+                res = G.push(j);
+                if (hn > 0) k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 0.0, wn, 1.0 / hn, wn);
+                if (res <= target || hn == 0.0) { ++j; break; }
+            }
+            std::vector<double> y = G.solve(j);
+            DBuf<double> &yd = st->shift;      // small device scratch (>= mS)
+            OT_HIP(hipMemcpyAsync(yd.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+            k_combine<T, T><<<grid1(n), BS, 0, s>>>(n, VS.p, n, j, yd.p, 0.0, tmpm2);
+            tri_apply(st, tmpm2, tmpm);
+            k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 1.0, tmpm, 1.0, w);
+            OT_HIP(hipStreamSynchronize(s));   // y lives in pageable host memory
+            if (res <= target || its >= maxit) break;
+            // restart: r = rhs - S w
+            schur_apply(st, w, VS.p);
+            k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 1.0, rhs, -1.0, VS.p);
+            beta = norm2<T>(st, VS.p, n);
+            if (beta <= target) break;
+        }
+        return its;
+    }
+
+    // ---- multigrid V-cycle on all K+1 slices at level l: x = M_l^-1 b
+    void cheb(ot_state *st, int l, const T *b, T *x, bool zero_x, int deg, double lo) {
+        const ot_mesh *m = st->mesh;
+        LevelView L = lview(m, l);
+        hipStream_t s = st->stream;
+        dim3 gr = grid2(L.n, K + 1);
+        const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+        k_cheb_init<T><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], b, x, lr[l], ld[l], theta, zero_x ? 1 : 0);
+        double rho_old = 1.0 / sigma;
+        T *d = ld[l], *d2 = ld2[l];
+        for (int it = 0; it < deg; ++it) {
+            const double rho_new = 1.0 / (2.0 * sigma - rho_old);
+            k_cheb_step<T><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
+                                             2.0 * rho_new / delta);
+            rho_old = rho_new;
+            std::swap(d, d2);
+        }
+    }
+
+    void vcycle(ot_state *st, int l, const T *b, T *x) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        if (l == nlev - 1) {
+            cheb(st, l, b, x, true, coarse_deg, coarse_lo_ratio * hi);
+            return;
+        }
+        const MGLevelDev &Lv = m->lv[l];
+        cheb(st, l, b, x, true, nu, lo_ratio * hi);
+        k_mg_restrict<T><<<grid2(Lv.n_next, K + 1), BS, 0, s>>>(lview(m, l), Lv.n_next, Lv.mem_ptr, Lv.mem_idx,
+                                                                lw[l], b, x, lb[l + 1]);
+        vcycle(st, l + 1, lb[l + 1], lx[l + 1]);
+        k_mg_prolong<T><<<grid2(Lv.n, K + 1), BS, 0, s>>>(Lv.n, Lv.n_next, Lv.agg, lx[l + 1], x);
+        cheb(st, l, b, x, false, nu, lo_ratio * hi);
+    }
+
+    // PCG on the K+1 slices A^k x^k = b^k (b already zero-mean); x zero-mean on exit
+    int pcg(ot_state *st, const T *b, T *x, double tol, int maxit) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        const int S = K + 1;
+        LevelView L0 = lview(m, 0);
+        dim3 gr = grid2(nf, S);
+        double *dsum = st->sums.p;               // scratch (>= S)
+        k_fill<T><<<grid1(nphi), BS, 0, s>>>(x, nphi, (T)0);
+        k_convert<T, T><<<grid1(nphi), BS, 0, s>>>(b, pr.p, nphi);
+        std::vector<double> bn(S), rz(S), alpha(S), beta(S);
+        std::vector<char> active(S, 1);
+        {
+            const double *h = st->red.fetch(slice_dots<T>(st, b, b, nf, S, dsum), S);
+            for (int k = 0; k < S; ++k) { bn[k] = std::sqrt(h[k]); active[k] = bn[k] > 0.0; }
+        }
+        if (std::none_of(active.begin(), active.end(), [](char c) { return c; })) return 0;
+        vcycle(st, 0, pr, pz);
+        {
+            const double *h = st->red.fetch(slice_dots<T>(st, pr.p, pz.p, nf, S, dsum), S);
+            for (int k = 0; k < S; ++k) rz[k] = h[k];
+        }
+        k_convert<T, T><<<grid1(nphi), BS, 0, s>>>(pz.p, pp.p, nphi);
+        int it = 0;
+        for (it = 1; it <= maxit; ++it) {
+            k_mg_apply<T><<<gr, BS, 0, s>>>(L0, lw[0], pp, pq);
+            const double *h = st->red.fetch(slice_dots<T>(st, pp.p, pq.p, nf, S, dsum), S);
+            for (int k = 0; k < S; ++k) alpha[k] = (active[k] && h[k] > 0.0) ? rz[k] / h[k] : 0.0;
+            OT_HIP(hipMemcpyAsync(coef.p, alpha.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+            k_pcg_xr<T><<<gr, BS, 0, s>>>(nf, coef, pp, pq, x, pr);
+            const double *h2 = st->red.fetch(slice_dots<T>(st, pr.p, pr.p, nf, S, dsum), S);
+            bool any = false;
+            for (int k = 0; k < S; ++k) {
+                if (active[k] && std::sqrt(std::max(h2[k], 0.0)) <= tol * bn[k]) active[k] = 0;
+                any = any || active[k];
+            }
+            if (!any) break;
+            vcycle(st, 0, pr, pz);
+            const double *h3 = st->red.fetch(slice_dots<T>(st, pr.p, pz.p, nf, S, dsum), S);
+            for (int k = 0; k < S; ++k) {
+                beta[k] = (active[k] && rz[k] != 0.0) ? h3[k] / rz[k] : 0.0;
+                if (active[k]) rz[k] = h3[k];
+            }
+            OT_HIP(hipMemcpyAsync(coef.p + S, beta.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+            k_pcg_p<T><<<gr, BS, 0, s>>>(nf, coef.p + S, pz, pp);
+        }
+        OT_HIP(hipStreamSynchronize(s));
+        return std::min(it, maxit);
+    }
+
+    void schur_apply_d(ot_state *st, const double *z, double *out) override {
+        k_convert<T, double><<<grid1(mrho), BS, 0, st->stream>>>(z, tmpm2, mrho);
+        schur_apply(st, tmpm2, probe);
+        k_convert<double, T><<<grid1(mrho), BS, 0, st->stream>>>(probe, out, mrho);
+    }
+    int schur_solve_d(ot_state *st, const double *rhs, double *z, double tol, int maxit) override {
+        k_convert<T, double><<<grid1(mrho), BS, 0, st->stream>>>(rhs, rhsS, mrho);
+        int its = gmres_schur(st, rhsS, zS, tol, maxit);
+        k_convert<double, T><<<grid1(mrho), BS, 0, st->stream>>>(zS, z, mrho);
+        return its;
+    }
+    void tri_diagonals_d(ot_state *st, double *a0, double *al, double *au) override {
+        OT_HIP(hipMemcpyAsync(a0, d0.p, mrho * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
+        OT_HIP(hipMemcpyAsync(al, dl.p, mrho * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
+        OT_HIP(hipMemcpyAsync(au, du.p, mrho * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
+    }
+    int laplace_solve_d(ot_state *st, const double *b, double *x, double tol, int maxit) override {
+        k_convert<T, double><<<grid1(nphi), BS, 0, st->stream>>>(b, bT, nphi);
+        int its = pcg(st, bT, px, tol, maxit);
+        k_convert<double, T><<<grid1(nphi), BS, 0, st->stream>>>(px, x, nphi);
+        return its;
+    }
+    size_t level_data_d(ot_state *st, int level, int what, double *out) override {
+        OT_REQUIRE(level >= 0 && level < nlev, OT_EINVAL, "bad level");
+        const MGLevelDev &L = st->mesh->lv[level];
+        const size_t n = (size_t)(K + 1) * (what == 0 ? L.ne : L.n);
+        if (out) k_convert<double, T><<<grid1(n), BS, 0, st->stream>>>(what == 0 ? lw[level] : ldinv[level], out, n);
+        return n;
+    }
+    void vcycle_d(ot_state *st, const double *b, double *x) override {
+        k_convert<T, double><<<grid1(nphi), BS, 0, st->stream>>>(b, pr, nphi);
+        vcycle(st, 0, pr, pz);
+        k_convert<double, T><<<grid1(nphi), BS, 0, st->stream>>>(pz, x, nphi);
+    }
+
+    // z = P_BB^-1 r (FP64 in/out)
+    void apply(ot_state *st, const double *r, double *z) override {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        const double tolS = st->opt.eps_in_S, tolA = st->opt.eps_in_A;
+        const int maxit = st->opt.max_inner;
+        k_convert<T, double><<<grid1(nphi), BS, 0, s>>>(r, cT, nphi);
+        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(r + nphi, dT, mrho);
+        // (i) pseudo-Schur solve
+        double *dsum = st->sums.p + 2 * (K + 2);
+        slice_sums<T>(st, dT.p, nullptr, nc, K, dsum);
+        dim3 gc = grid2(nc, K);
+        k_schur_rhs<T><<<gc, BS, 0, s>>>(m->ac, nc, st->area, dsum, rhoT, dT, rhsS);
+        st->acc.inner_S_iters += gmres_schur(st, rhsS, zS, tolS, maxit);
+        // (ii) y = P^T M'^-1 A~ z
+        k_coarse_lap_scaled<T><<<gc, BS, 0, s>>>(mesh_view(m), zS, wc, yT);
+        double *ys = st->sums.p + 3 * (K + 2);
+        slice_sums<T>(st, yT.p, m->ac, nc, K, ys);
+        k_slice_shift<T><<<gc, BS, 0, s>>>(nc, ys, 1.0 / st->area, yT);
+        // (iii) b = c - B^T y, projected to zero sum per slice
+        dim3 gf = grid2(nf, K + 1);
+        k_bt_rhs<T><<<gf, BS, 0, s>>>(mesh_view(m), K, st->dt, cT, yT, g, bT);
+        double *bs = st->sums.p + 4 * (K + 2);
+        slice_sums<T>(st, bT.p, nullptr, nf, K + 1, bs);
+        k_slice_shift<T><<<gf, BS, 0, s>>>(nf, bs, 1.0 / nf, bT);
+        // (iv) K+1 Laplacian solves, zero-sum solutions
+        st->acc.inner_A_iters += pcg(st, bT, px, tolA, maxit);
+        slice_sums<T>(st, px.p, nullptr, nf, K + 1, bs);
+        k_slice_shift<T><<<gf, BS, 0, s>>>(nf, bs, 1.0 / nf, px);
+        k_convert<double, T><<<grid1(nphi), BS, 0, s>>>(px, z, nphi);
+        k_convert<double, T><<<grid1(mrho), BS, 0, s>>>(yT, z + nphi, mrho);
+        st->acc.prec_applies++;
+    }
+};
+
+namespace otbb {
+
+static void ensure_prec(ot_state *st) {
+    int kind = st->opt.precision;
+    if (!st->prec || st->prec_kind != kind) {
+        if (kind == OT_MIXED) st->prec.reset(new BBPrec<float>());
+        else st->prec.reset(new BBPrec<double>());
+        st->prec_kind = kind;
+        st->lin_valid = false;
+    }
+}
+
+static void linearize(ot_state *st) {
+    ensure_prec(st);
+    if (!st->lin_valid) {
+        st->prec->setup(st);
+        st->lin_valid = true;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES on J_P with the BB preconditioner: x = J_P^-1 b (x zero start)
+// ---------------------------------------------------------------------------
+static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int maxit, double *res_out) {
+    hipStream_t s = st->stream;
+    const size_t N = st->N;
+    const int m = std::max(1, st->opt.restart);
+    if (st->V.n < (size_t)(m + 1) * N) st->V.alloc((size_t)(m + 1) * N);
+    if (st->Z.n < (size_t)m * N) st->Z.alloc((size_t)m * N);
+    k_fill<double><<<grid1(N), BS, 0, s>>>(x, N, 0.0);
+    double beta = norm2<double>(st, b, N);
+    *res_out = beta;
+    if (beta <= tol_abs) return 0;
+    k_convert<double, double><<<grid1(N), BS, 0, s>>>(b, st->V.p, N);
+    Givens G(m);
+    int its = 0;
+    double res = beta;
+    std::vector<double> h(m + 1);
+    while (its < maxit) {
+        k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, st->V.p, 1.0 / beta, st->V.p);
+        G.reset(beta);
+        int j = 0;
+        for (; j < m && its < maxit; ++j) {
+            double *zj = st->Z.p + (size_t)j * N;
+            st->prec->apply(st, st->V.p + (size_t)j * N, zj);
+            double *wn = st->V.p + (size_t)(j + 1) * N;
+            apply_saddle(st, zj, wn);
+            double hn = cgs2<double>(st, st->V.p, N, j + 1, wn, N, h.data());
+            for (int i = 0; i <= j; ++i) G.h(i, j) = h[i];
+            G.h(j + 1, j) = hn;
+            ++its;
+            res = G.push(j);
+            if (hn > 0) k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, wn, 1.0 / hn, wn);
+            if (st->opt.verbose > 1) fprintf(stderr, "    fgmres it %d res %.3e target %.3e\n", its, res, tol_abs);
+            if (res <= tol_abs || hn == 0.0) { ++j; break; }
+        }
+        std::vector<double> y = G.solve(j);
+        OT_HIP(hipMemcpyAsync(st->shift.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+        k_combine<double, double><<<grid1(N), BS, 0, s>>>(N, st->Z.p, N, j, st->shift.p, 1.0, x);
+        OT_HIP(hipStreamSynchronize(s));
+        if (res <= tol_abs || its >= maxit) break;
+        // restart with the true residual
+        apply_saddle(st, x, st->V.p);
+        k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 1.0, b, -1.0, st->V.p);
+        beta = norm2<double>(st, st->V.p, N);
+        res = beta;
+        if (beta <= tol_abs) break;
+    }
+    *res_out = res;
+    return its;
+}
+
+// Solve J_s (dphi; drho) = (f; g~) through the projected system and the
+// recovery of Sec. 4.4.1-2.  rhs holds (f; g~) on entry (g~ also in gt);
+// solution written to sol.  Returns FGMRES iterations; sets last_converged.
+static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
+    const ot_mesh *m = st->mesh;
+    hipStream_t s = st->stream;
+    const int K = st->K, nf = m->h.nf, nc = m->h.nc;
+    MeshView mv = mesh_view(m);
+    StateView sv = st->view();
+    // projected right-hand side (f; P g~)
+    double *cs = st->sums.p;
+    slice_sums<double>(st, st->rhs.p + st->nphi, nullptr, nc, K, cs);
+    k_proj_fix<double><<<grid2(nc, K), BS, 0, s>>>(m->ac, nc, cs, st->area, st->rhs.p + st->nphi);
+    linearize(st);
+    double t0 = now_s();
+    double res = 0.0;
+    const double tol = st->opt.eps_out * rhs_norm_abs;
+    int its = fgmres(st, st->rhs, st->sol, tol, st->opt.max_fgmres, &res);
+    st->acc.seconds_linear += now_s() - t0;
+    st->acc.outer_iters += its;
+    st->acc.linear_systems++;
+    st->last_iters = its;
+    st->last_relres = rhs_norm_abs > 0 ? res / rhs_norm_abs : 0.0;
+    st->last_converged = res <= tol;
+    // recovery: drho <- P^T drho; dphi_bar = dphi_hat - area mean; shift
+    double *drho = st->sol.p + st->nphi, *dphi = st->sol.p;
+    slice_sums<double>(st, drho, m->ac, nc, K, cs);
+    k_slice_shift<double><<<grid2(nc, K), BS, 0, s>>>(nc, cs, 1.0 / st->area, drho);
+    double *ps = st->sums.p + (K + 2);
+    slice_sums<double>(st, dphi, m->a, nf, K + 1, ps);
+    k_slice_shift<double><<<grid2(nf, K + 1), BS, 0, s>>>(nf, ps, 1.0 / st->area, dphi);
+    dim3 gc = grid2(nc, K);
+    k_opB<<<gc, BS, 0, s>>>(mv, sv, dphi, nullptr, nullptr, 0, st->tmpr, nullptr);
+    k_recover_r<<<gc, BS, 0, s>>>(nc, m->ac, st->gt, st->tmpr, drho, sv, st->red.part);
+    double *ls = st->sums.p + 2 * (K + 2);
+    k_seg_final<<<K, BS, 0, s>>>(st->red.part, gc.x, ls);
+    const double *lam = st->red.fetch(ls, K);
+    std::vector<double> shift(K + 1, 0.0);
+    for (int k = 1; k <= K; ++k) shift[k] = shift[k - 1] + st->dt * lam[k - 1] / st->area;
+    OT_HIP(hipMemcpyAsync(st->shift.p, shift.data(), (K + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+    k_add_shift<<<grid2(nf, K + 1), BS, 0, s>>>(nf, st->shift, dphi);
+    OT_HIP(hipStreamSynchronize(s));
+    return its;
+}
+
+static void renormalize(ot_state *st) {
+    const ot_mesh *m = st->mesh;
+    double *mass = st->sums.p;
+    slice_sums<double>(st, st->rho.p, m->ac, m->h.nc, st->K, mass);
+    k_renorm<<<grid2(m->h.nc, st->K), BS, 0, st->stream>>>(m->h.nc, mass, st->m0, st->rho);
+}
+
+// One inexact Newton step (returns OT_OK / OT_ELINSOLVE)
+static int newton_step(ot_state *st, double *res_before) {
+    const ot_mesh *m = st->mesh;
+    hipStream_t s = st->stream;
+    const int K = st->K, nc = m->h.nc;
+    MeshView mv = mesh_view(m);
+    StateView sv = st->view();
+    double t0 = now_s();
+    const double fn = residual(st);
+    if (res_before) *res_before = fn;
+    // f = -F_phi, g~ = -F_rho + a' F_s / rho
+    k_neg_copy<<<grid1(st->nphi), BS, 0, s>>>(st->nphi, st->F, st->rhs);
+    dim3 gc = grid2(nc, K);
+    k_newton_rhs<<<gc, BS, 0, s>>>(mv, sv, st->F, st->rhs, st->gt, st->red.part, st->nphi, st->mrho);
+    st->lin_valid = false;
+    st->acc.seconds_setup += 0.0;
+    double ts = now_s();
+    linearize(st);
+    OT_HIP(hipStreamSynchronize(s));
+    st->acc.seconds_setup += now_s() - ts;
+    int its = solve_newton_system(st, fn);
+    int rc = OT_OK;
+    if (!st->last_converged) {
+        st->acc.failures++;
+        if (!(st->last_relres <= 1e-2)) return OT_ELINSOLVE;   // state untouched
+        rc = OT_ELINSOLVE;
+    }
+    (void)its;
+    // ds and the step length
+    double *drho = st->sol.p + st->nphi;
+    int nblk = grid1(st->mrho);
+    k_ds_ratio<<<nblk, BS, 0, s>>>(st->mrho, sv, st->mu, drho, st->ds, st->red.part);
+    k_min_final<<<1, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
+    const double amax = st->red.fetch(st->red.dev, 1)[0];
+    const double alpha = std::min(1.0, st->opt.frac_to_boundary * amax);
+    k_axpy<<<grid1(st->nphi), BS, 0, s>>>(st->nphi, alpha, st->sol, st->phi);
+    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha, drho, st->rho);
+    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha, st->ds, st->s);
+    renormalize(st);
+    OT_HIP(hipStreamSynchronize(s));
+    st->lin_valid = false;
+    st->acc.newton_steps++;
+    if (st->opt.verbose)
+        fprintf(stderr, "  mu %.3e |F| %.3e fgmres %d relres %.2e alpha %.3f (%.3fs)\n", st->mu, fn,
+                st->last_iters, st->last_relres, alpha, now_s() - t0);
+    return rc;
+}
+
+// outputs: kinetic energy, dual value; optional normalised phi to dst
+static void outputs(ot_state *st, double *cost, double *dual) {
+    const ot_mesh *m = st->mesh;
+    hipStream_t s = st->stream;
+    const int K = st->K, nf = m->h.nf, nc = m->h.nc;
+    MeshView mv = mesh_view(m);
+    StateView sv = st->view();
+    dim3 ge = grid2(m->h.ne, K + 1);
+    k_ke_partial<<<ge, BS, 0, s>>>(mv, sv, st->red.part);
+    double *ke = st->red.seg_final(1, ge.x * ge.y, 0);
+    double kev = 0.5 * st->dt * st->red.fetch(ke, 1)[0];
+    // D* terms per coarse cell
+    double *b = st->tmpN.p;
+    const double *pf = st->phi.p, *pl = st->phi.p + (size_t)K * nf;
+    k_boundary_terms<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, sv, pf, pl, b, b + nc, b + 2 * nc, b + 3 * nc);
+    std::vector<double> h(4 * (size_t)nc), rin(nc), rf(nc);
+    OT_HIP(hipMemcpyAsync(h.data(), b, 4 * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    OT_HIP(hipMemcpyAsync(rin.data(), st->rin.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    OT_HIP(hipMemcpyAsync(rf.data(), st->rf.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    OT_HIP(hipStreamSynchronize(s));
+    double d = 0.0;
+    for (int j = 0; j < nc; ++j)
+        d += h[nc + j] * rf[j] - h[j] * rin[j] - 0.25 * st->dt * (rin[j] * h[2 * nc + j] + rf[j] * h[3 * nc + j]);
+    if (cost) *cost = kev;
+    if (dual) *dual = d;
+}
+
+static void normalized_phi(ot_state *st, double *dst) {
+    const ot_mesh *m = st->mesh;
+    const int K = st->K, nf = m->h.nf;
+    double *ps = st->sums.p;
+    slice_sums<double>(st, st->phi.p, m->a, nf, K + 1, ps);
+    const double *h = st->red.fetch(ps, K + 1);
+    double tot = 0.0;
+    for (int k = 0; k <= K; ++k) tot += h[k];
+    const double c = tot / ((K + 1) * st->area);
+    k_convert<double, double><<<grid1(st->nphi), BS, 0, st->stream>>>(st->phi, dst, st->nphi);
+    k_fill<double><<<1, BS, 0, st->stream>>>(st->shift.p, K + 2, c);
+    k_slice_shift<double><<<grid2(nf, K + 1), BS, 0, st->stream>>>(nf, st->shift, 1.0, dst);
+    OT_HIP(hipStreamSynchronize(st->stream));
+}
+
+}  // namespace otbb
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+namespace {
+
+template <typename F>
+int guard(F &&f) {
+    try {
+        f();
+        return OT_OK;
+    } catch (const OtError &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return OT_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return OT_EDEVICE;
+    }
+}
+
+hipStream_t opt_stream(const ot_options *o) { return o ? (hipStream_t)o->stream : nullptr; }
+
+void copy_in(double *dst, const double *src, size_t n, int mem_kind, hipStream_t s) {
+    OT_HIP(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          mem_kind == OT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+void copy_out(double *dst, const double *src, size_t n, int mem_kind, hipStream_t s) {
+    OT_HIP(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          mem_kind == OT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+}
+
+void check_options(const ot_options &o) {
+    OT_REQUIRE(o.tol > 0 && o.eps_out > 0 && o.eps_in_S > 0 && o.eps_in_A > 0, OT_EINVAL, "tolerances must be > 0");
+    OT_REQUIRE(o.mu0 > 0 && o.mu_factor > 0 && o.mu_factor < 1, OT_EINVAL, "bad mu schedule");
+    OT_REQUIRE(o.frac_to_boundary > 0 && o.frac_to_boundary < 1, OT_EINVAL, "bad step fraction");
+    OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart <= 60 && o.max_inner >= 1 &&
+                   o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart <= 60,
+               OT_EINVAL, "bad iteration caps");
+    OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
+    OT_REQUIRE(o.mem_kind == OT_HOST || o.mem_kind == OT_DEVICE, OT_EINVAL, "bad mem_kind");
+}
+
+// host copy of marginals for validation (from host or device memory)
+std::vector<double> fetch_vec(const double *p, size_t n, int mem_kind, hipStream_t s) {
+    std::vector<double> h(n);
+    if (mem_kind == OT_DEVICE) {
+        OT_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+    } else {
+        std::memcpy(h.data(), p, n * sizeof(double));
+    }
+    return h;
+}
+
+void validate_marginals(const ot_mesh *m, const std::vector<double> &ri, const std::vector<double> &rf) {
+    double mi = 0, mf = 0;
+    for (int j = 0; j < m->h.nc; ++j) {
+        OT_REQUIRE(std::isfinite(ri[j]) && ri[j] >= 0 && std::isfinite(rf[j]) && rf[j] >= 0, OT_ENEG,
+                   "marginals must be finite and >= 0");
+        mi += m->h.ac[j] * ri[j];
+        mf += m->h.ac[j] * rf[j];
+    }
+    OT_REQUIRE(mi > 0, OT_ENEG, "marginal mass must be > 0");
+    OT_REQUIRE(std::fabs(mi - mf) <= 1e-12 * mi, OT_EMASS, "marginals have different mass");
+}
+
+ot_state *create_state(const ot_mesh *m, const double *rho_in, const double *rho_f, int K, const ot_options &o) {
+    OT_REQUIRE(m && rho_in && rho_f, OT_EINVAL, "null argument");
+    OT_REQUIRE(K >= 1, OT_EINVAL, "K must be >= 1");
+    check_options(o);
+    hipStream_t s = opt_stream(&o);
+    auto ri = fetch_vec(rho_in, m->h.nc, o.mem_kind, s);
+    auto rf = fetch_vec(rho_f, m->h.nc, o.mem_kind, s);
+    validate_marginals(m, ri, rf);
+    std::unique_ptr<ot_state> st(new ot_state());
+    st->mesh = m;
+    st->K = K;
+    st->opt = o;
+    st->stream = s;
+    const int nf = m->h.nf, nc = m->h.nc;
+    st->nphi = (size_t)(K + 1) * nf;
+    st->mrho = (size_t)K * nc;
+    st->N = st->nphi + st->mrho;
+    st->dt = 1.0 / (K + 1);
+    st->area = m->area;
+    st->mu = o.mu0;
+    st->m0 = 0.0;
+    for (int j = 0; j < nc; ++j) st->m0 += m->h.ac[j] * ri[j];
+    st->phi.alloc(st->nphi); st->rho.alloc(st->mrho); st->s.alloc(st->mrho);
+    st->rin.upload(ri, s); st->rf.upload(rf, s);
+    st->F.alloc(st->nphi + 2 * st->mrho);
+    st->rhs.alloc(st->N); st->sol.alloc(st->N); st->gt.alloc(st->mrho);
+    st->tmpN.alloc(std::max(st->N, (size_t)6 * nc)); st->tmpr.alloc(st->mrho); st->ds.alloc(st->mrho);
+    st->sums.alloc(8 * (K + 2) + 256);
+    st->shift.alloc(std::max(K + 2, 128));
+    size_t np = (size_t)(ceil_div(std::max(std::max(nf, nc), std::max(m->h.ne, 1)), BS) + 1) * (2 * K + 4) +
+                (size_t)72 * 1024;
+    st->red.init(np, std::max<size_t>(256, 8 * (size_t)(K + 2)), s);
+    // start point: phi = 0, rho = m0/|Omega|, s = mu0/rho
+    k_fill<double><<<grid1(st->nphi), BS, 0, s>>>(st->phi, st->nphi, 0.0);
+    k_fill<double><<<grid1(st->mrho), BS, 0, s>>>(st->rho, st->mrho, st->m0 / st->area);
+    k_fill<double><<<grid1(st->mrho), BS, 0, s>>>(st->s, st->mrho, o.mu0 * st->area / st->m0);
+    OT_HIP(hipStreamSynchronize(s));
+    return st.release();
+}
+
+// continuation driver (Sec. 2.4); returns OT code
+int run_ipm(ot_state *st, double tol) {
+    const ot_options &o = st->opt;
+    double t0 = now_s();
+    int rc = OT_OK;
+    st->mu = o.mu0;
+    for (int l = 0; l < 400; ++l) {
+        const bool last = st->mu < tol;
+        const double tl = (last && o.final_tol > 0) ? o.final_tol : tol;
+        bool ok = false;
+        for (int it = 0; it <= o.max_newton; ++it) {
+            double fn = residual(st);
+            st->acc.final_residual = fn;
+            if (fn <= tl) { ok = true; break; }
+            if (it == o.max_newton) break;
+            int r = newton_step(st, nullptr);
+            if (r != OT_OK && st->last_relres > 1e-2) { rc = r; break; }
+        }
+        st->acc.ip_steps++;
+        if (rc != OT_OK) break;
+        if (!ok) { rc = OT_ENEWTON; break; }
+        if (last) break;
+        st->mu *= o.mu_factor;
+    }
+    st->acc.mu = st->mu;
+    st->acc.seconds_total += now_s() - t0;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ot_options_default(ot_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6; o->eps_out = 1e-5; o->eps_in_S = 1e-1; o->eps_in_A = 1e-2;
+    o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0;
+    o->max_fgmres = 400; o->restart = 40; o->max_inner = 200; o->max_newton = 20; o->inner_restart = 20;
+    o->precision = OT_MIXED; o->mem_kind = OT_HOST; o->verbose = 0; o->stream = nullptr;
+}
+
+const char *ot_last_error(void) { return g_last_error.c_str(); }
+
+int ot_mesh_create(const ot_mesh_desc *d, ot_mesh **out) {
+    return guard([&] {
+        OT_REQUIRE(d && out, OT_EINVAL, "null argument");
+        *out = nullptr;
+        OT_REQUIRE(d->n_fine > 0 && d->n_coarse > 0 && d->n_overlap >= 0 && d->n_fedge >= 0 && d->n_cedge >= 0,
+                   OT_EINVAL, "bad sizes");
+        OT_REQUIRE(d->fine_area && d->coarse_area && (d->n_overlap == 0 || (d->ov_fine && d->ov_coarse && d->ov_area)) &&
+                       (d->n_fedge == 0 || (d->fe_cell && d->fe_rho && d->fe_len && d->fe_dist && d->fe_lambda)) &&
+                       (d->n_cedge == 0 || (d->ce_cell && d->ce_len && d->ce_dist && d->ce_lambda)),
+                   OT_EINVAL, "null array in mesh description");
+        std::unique_ptr<ot_mesh> m(new ot_mesh());
+        MeshHost &h = m->h;
+        h.nf = d->n_fine; h.nc = d->n_coarse; h.ne = d->n_fedge; h.nce = d->n_cedge;
+        h.a.assign(d->fine_area, d->fine_area + h.nf);
+        h.ac.assign(d->coarse_area, d->coarse_area + h.nc);
+        h.ov_f.assign(d->ov_fine, d->ov_fine + d->n_overlap);
+        h.ov_c.assign(d->ov_coarse, d->ov_coarse + d->n_overlap);
+        h.ov_a.assign(d->ov_area, d->ov_area + d->n_overlap);
+        for (int e = 0; e < h.ne; ++e) {
+            h.eK.push_back(d->fe_cell[2 * e]); h.eL.push_back(d->fe_cell[2 * e + 1]);
+            h.erK.push_back(d->fe_rho[2 * e]); h.erL.push_back(d->fe_rho[2 * e + 1]);
+        }
+        h.elen.assign(d->fe_len, d->fe_len + h.ne);
+        h.edist.assign(d->fe_dist, d->fe_dist + h.ne);
+        h.elam.assign(d->fe_lambda, d->fe_lambda + h.ne);
+        for (int e = 0; e < h.nce; ++e) { h.ceI.push_back(d->ce_cell[2 * e]); h.ceJ.push_back(d->ce_cell[2 * e + 1]); }
+        h.celen.assign(d->ce_len, d->ce_len + h.nce);
+        h.cedist.assign(d->ce_dist, d->ce_dist + h.nce);
+        h.celam.assign(d->ce_lambda, d->ce_lambda + h.nce);
+        mesh_finalize(m.get());
+        *out = m.release();
+    });
+}
+
+int ot_mesh_create_structured(int32_t n, int32_t cartesian, ot_mesh **out) {
+    return guard([&] {
+        OT_REQUIRE(out, OT_EINVAL, "null argument");
+        *out = nullptr;
+        OT_REQUIRE(n >= 2 && n <= 16384, OT_EINVAL, "n out of range");
+        std::unique_ptr<ot_mesh> m(new ot_mesh());
+        structured_desc(n, cartesian != 0, m->h);
+        mesh_finalize(m.get());
+        *out = m.release();
+    });
+}
+
+void ot_mesh_destroy(ot_mesh *m) { delete m; }
+
+int ot_mesh_sizes(const ot_mesh *m, int32_t *nf, int32_t *nc, int32_t *ne, int32_t *nce) {
+    return guard([&] {
+        OT_REQUIRE(m, OT_EINVAL, "null mesh");
+        if (nf) *nf = m->h.nf;
+        if (nc) *nc = m->h.nc;
+        if (ne) *ne = m->h.ne;
+        if (nce) *nce = m->h.nce;
+    });
+}
+
+int ot_state_create(const ot_mesh *m, const double *rho_in, const double *rho_f, int32_t K,
+                    const ot_options *opt, ot_state **out) {
+    return guard([&] {
+        OT_REQUIRE(out, OT_EINVAL, "null argument");
+        *out = nullptr;
+        ot_options o;
+        if (opt) o = *opt; else ot_options_default(&o);
+        *out = create_state(m, rho_in, rho_f, K, o);
+    });
+}
+
+void ot_state_destroy(ot_state *st) { delete st; }
+
+int ot_state_sizes(const ot_state *st, int64_t *n_phi, int64_t *m_rho) {
+    return guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        if (n_phi) *n_phi = (int64_t)st->nphi;
+        if (m_rho) *m_rho = (int64_t)st->mrho;
+    });
+}
+
+int ot_state_set_options(ot_state *st, const ot_options *opt) {
+    return guard([&] {
+        OT_REQUIRE(st && opt, OT_EINVAL, "null argument");
+        check_options(*opt);
+        OT_REQUIRE((hipStream_t)opt->stream == st->stream, OT_EINVAL, "stream of a state cannot change");
+        const int old_prec = st->opt.precision, old_inner = st->opt.inner_restart;
+        st->opt = *opt;
+        if (old_prec != opt->precision || old_inner != opt->inner_restart) {
+            st->prec.reset();
+            st->prec_kind = -1;
+        }
+        st->lin_valid = false;
+    });
+}
+
+int ot_state_export(const ot_state *st, double *phi, double *rho, double *s, double *mu) {
+    return guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        const int mk = st->opt.mem_kind;
+        if (phi) copy_out(phi, st->phi, st->nphi, mk, st->stream);
+        if (rho) copy_out(rho, st->rho, st->mrho, mk, st->stream);
+        if (s) copy_out(s, st->s, st->mrho, mk, st->stream);
+        if (mu) *mu = st->mu;
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_state_import(ot_state *st, const double *phi, const double *rho, const double *s, double mu) {
+    return guard([&] {
+        OT_REQUIRE(st && phi && rho && s, OT_EINVAL, "null argument");
+        OT_REQUIRE(mu > 0, OT_EINVAL, "mu must be > 0");
+        const int mk = st->opt.mem_kind;
+        auto hr = fetch_vec(rho, st->mrho, mk, st->stream);
+        auto hs = fetch_vec(s, st->mrho, mk, st->stream);
+        for (size_t q = 0; q < st->mrho; ++q)
+            OT_REQUIRE(std::isfinite(hr[q]) && hr[q] > 0 && std::isfinite(hs[q]) && hs[q] > 0, OT_ENEG,
+                       "imported rho and s must be finite and > 0");
+        copy_in(st->phi, phi, st->nphi, mk, st->stream);
+        copy_in(st->rho, rho, st->mrho, mk, st->stream);
+        copy_in(st->s, s, st->mrho, mk, st->stream);
+        st->mu = mu;
+        st->lin_valid = false;
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_state_set_mu(ot_state *st, double mu) {
+    return guard([&] {
+        OT_REQUIRE(st && mu > 0, OT_EINVAL, "bad argument");
+        st->mu = mu;
+    });
+}
+
+int ot_residual(ot_state *st, double *F, double *nrm) {
+    return guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        double n = residual(st);
+        if (nrm) *nrm = n;
+        if (F) copy_out(F, st->F, st->nphi + 2 * st->mrho, st->opt.mem_kind, st->stream);
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm) {
+    int rc = OT_OK;
+    int g = guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        ot_stats before = st->acc;
+        rc = newton_step(st, res_norm);
+        if (stats) {
+            *stats = st->acc;
+            stats->outer_iters -= before.outer_iters;
+            stats->inner_S_iters -= before.inner_S_iters;
+            stats->inner_A_iters -= before.inner_A_iters;
+            stats->prec_applies -= before.prec_applies;
+            stats->linear_systems -= before.linear_systems;
+            stats->newton_steps -= before.newton_steps;
+            stats->failures -= before.failures;
+        }
+        if (rc != OT_OK) set_last_error("FGMRES did not reach eps_out");
+    });
+    return g != OT_OK ? g : rc;
+}
+
+int ot_apply_saddle(ot_state *st, const double *x, double *y) {
+    return guard([&] {
+        OT_REQUIRE(st && x && y, OT_EINVAL, "null argument");
+        const int mk = st->opt.mem_kind;
+        copy_in(st->tmpN, x, st->N, mk, st->stream);
+        apply_saddle(st, st->tmpN, st->rhs);
+        copy_out(y, st->rhs, st->N, mk, st->stream);
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_apply_schur_prec(ot_state *st, const double *r, double *z) {
+    return guard([&] {
+        OT_REQUIRE(st && r && z, OT_EINVAL, "null argument");
+        const int mk = st->opt.mem_kind;
+        linearize(st);
+        copy_in(st->tmpN, r, st->N, mk, st->stream);
+        st->prec->apply(st, st->tmpN, st->rhs);
+        copy_out(z, st->rhs, st->N, mk, st->stream);
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_outputs(ot_state *st, double *cost, double *dual, double *phi_out) {
+    return guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        outputs(st, cost, dual);
+        if (phi_out) {
+            normalized_phi(st, st->tmpN);
+            copy_out(phi_out, st->tmpN, st->nphi, st->opt.mem_kind, st->stream);
+            OT_HIP(hipStreamSynchronize(st->stream));
+        }
+    });
+}
+
+int ot_solve(const ot_mesh *m, const double *rho_in, const double *rho_f, int32_t K, double tol,
+             const ot_options *opt, double *rho_out, double *phi_out, double *cost_out, ot_stats *stats) {
+    int rc = OT_OK;
+    int g = guard([&] {
+        ot_options o;
+        if (opt) o = *opt; else ot_options_default(&o);
+        if (tol > 0) o.tol = tol;
+        std::unique_ptr<ot_state> st(create_state(m, rho_in, rho_f, K, o));
+        rc = run_ipm(st.get(), o.tol);
+        double cost = 0, dual = 0;
+        outputs(st.get(), &cost, &dual);
+        st->acc.cost = cost; st->acc.dual = dual; st->acc.gap = cost - dual;
+        if (cost_out) *cost_out = cost;
+        if (rho_out) copy_out(rho_out, st->rho, st->mrho, o.mem_kind, st->stream);
+        if (phi_out) {
+            normalized_phi(st.get(), st->tmpN);
+            copy_out(phi_out, st->tmpN, st->nphi, o.mem_kind, st->stream);
+        }
+        OT_HIP(hipStreamSynchronize(st->stream));
+        if (stats) *stats = st->acc;
+        if (rc == OT_ELINSOLVE) set_last_error("FGMRES failed");
+        if (rc == OT_ENEWTON) set_last_error("Newton iteration cap reached");
+    });
+    return g != OT_OK ? g : rc;
+}
+
+int ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes, const double *const *rho_in,
+                     const double *const *rho_f, const int32_t *K, double tol, const ot_options *opt,
+                     double *const *rho_out, double *const *phi_out, double *costs, ot_stats *stats) {
+    int rc = OT_OK;
+    int g = guard([&] {
+        OT_REQUIRE(nprob >= 0 && (nprob == 0 || (meshes && rho_in && rho_f && K)), OT_EINVAL, "null argument");
+        for (int p = 0; p < nprob; ++p) {
+            int r = ot_solve(meshes[p], rho_in[p], rho_f[p], K[p], tol, opt, rho_out ? rho_out[p] : nullptr,
+                             phi_out ? phi_out[p] : nullptr, costs ? costs + p : nullptr, stats ? stats + p : nullptr);
+            if (r != OT_OK && rc == OT_OK) rc = r;
+        }
+    });
+    return g != OT_OK ? g : rc;
+}
+
+int ot_gradient(ot_state *st, double *g_in, double *g_f) {
+    return guard([&] {
+        OT_REQUIRE(st && g_in && g_f, OT_EINVAL, "null argument");
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        const int K = st->K, nf = m->h.nf, nc = m->h.nc;
+        MeshView mv = mesh_view(m);
+        StateView sv = st->view();
+        // adjoint right-hand side (0; dt a' s), projected system + recovery
+        k_fill<double><<<grid1(st->nphi), BS, 0, s>>>(st->rhs, st->nphi, 0.0);
+        std::vector<double> ac(m->h.ac);
+        std::vector<double> sh(st->mrho);
+        OT_HIP(hipMemcpyAsync(sh.data(), st->s.p, st->mrho * sizeof(double), hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+        double nrm = 0.0;
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < nc; ++j) {
+                double v = st->dt * ac[j] * sh[(size_t)k * nc + j];
+                sh[(size_t)k * nc + j] = v;
+                nrm += v * v;
+            }
+        OT_HIP(hipMemcpyAsync(st->gt.p, sh.data(), st->mrho * sizeof(double), hipMemcpyHostToDevice, s));
+        OT_HIP(hipMemcpyAsync(st->rhs.p + st->nphi, sh.data(), st->mrho * sizeof(double), hipMemcpyHostToDevice, s));
+        st->lin_valid = false;
+        linearize(st);
+        solve_newton_system(st, std::sqrt(nrm));
+        // corrections and envelope terms
+        double *b = st->tmpN.p;
+        const double *q1 = st->sol.p, *qK = st->sol.p + (size_t)K * nf;
+        const double *p1 = st->phi.p, *pK = st->phi.p + (size_t)K * nf;
+        k_adjoint_corr<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, p1, q1, 1.0, st->dt, b);
+        k_adjoint_corr<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, pK, qK, -1.0, st->dt, b + nc);
+        k_boundary_terms<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, sv, p1, pK, b + 2 * nc, b + 3 * nc, b + 4 * nc,
+                                                          b + 5 * nc);
+        std::vector<double> h(6 * (size_t)nc);
+        OT_HIP(hipMemcpyAsync(h.data(), b, 6 * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+        std::vector<double> gi(nc), gf(nc);
+        for (int j = 0; j < nc; ++j) {
+            gi[j] = -h[2 * nc + j] - 0.25 * st->dt * h[4 * nc + j] - h[j];
+            gf[j] = h[3 * nc + j] - 0.25 * st->dt * h[5 * nc + j] - h[nc + j];
+        }
+        double aa = 0, ai = 0, af = 0;
+        for (int j = 0; j < nc; ++j) { aa += ac[j] * ac[j]; ai += ac[j] * gi[j]; af += ac[j] * gf[j]; }
+        for (int j = 0; j < nc; ++j) { gi[j] -= ac[j] * ai / aa; gf[j] -= ac[j] * af / aa; }
+        if (st->opt.mem_kind == OT_DEVICE) {
+            OT_HIP(hipMemcpyAsync(g_in, gi.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+            OT_HIP(hipMemcpyAsync(g_f, gf.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+            OT_HIP(hipStreamSynchronize(s));
+        } else {
+            std::memcpy(g_in, gi.data(), nc * sizeof(double));
+            std::memcpy(g_f, gf.data(), nc * sizeof(double));
+        }
+        st->lin_valid = false;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Inspection entry points (include/otbb_debug.h): host pointers in and out
+// ---------------------------------------------------------------------------
+extern "C" {
+
+static int dbg_vec(ot_state *st, const double *in, size_t nin, double *out, size_t nout,
+                   const std::function<void(const double *, double *)> &f) {
+    return guard([&] {
+        OT_REQUIRE(st && in && out, OT_EINVAL, "null argument");
+        linearize(st);
+        OT_HIP(hipMemcpyAsync(st->tmpN.p, in, nin * sizeof(double), hipMemcpyHostToDevice, st->stream));
+        f(st->tmpN.p, st->rhs.p);
+        OT_HIP(hipMemcpyAsync(out, st->rhs.p, nout * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int otbb_debug_schur_apply(ot_state *st, const double *z, double *out) {
+    return dbg_vec(st, z, st ? st->mrho : 0, out, st ? st->mrho : 0,
+                   [&](const double *a, double *b) { st->prec->schur_apply_d(st, a, b); });
+}
+
+int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double tol, int32_t maxit,
+                           int32_t *iters) {
+    int its = 0;
+    int rc = dbg_vec(st, rhs, st ? st->mrho : 0, z, st ? st->mrho : 0,
+                     [&](const double *a, double *b) { its = st->prec->schur_solve_d(st, a, b, tol, maxit); });
+    if (iters) *iters = its;
+    return rc;
+}
+
+int otbb_debug_tri_diagonals(ot_state *st, double *d0, double *dl, double *du) {
+    return guard([&] {
+        OT_REQUIRE(st && d0 && dl && du, OT_EINVAL, "null argument");
+        linearize(st);
+        double *b = st->tmpN.p;
+        const size_t m = st->mrho;
+        OT_REQUIRE(st->tmpN.n >= 3 * m, OT_EINVAL, "internal: scratch too small");
+        st->prec->tri_diagonals_d(st, b, b + m, b + 2 * m);
+        OT_HIP(hipMemcpyAsync(d0, b, m * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        OT_HIP(hipMemcpyAsync(dl, b + m, m * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        OT_HIP(hipMemcpyAsync(du, b + 2 * m, m * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int otbb_debug_laplace_solve(ot_state *st, const double *b, double *x, double tol, int32_t maxit,
+                             int32_t *iters) {
+    int its = 0;
+    int rc = dbg_vec(st, b, st ? st->nphi : 0, x, st ? st->nphi : 0,
+                     [&](const double *a, double *o) { its = st->prec->laplace_solve_d(st, a, o, tol, maxit); });
+    if (iters) *iters = its;
+    return rc;
+}
+
+int otbb_debug_mg_level(ot_state *st, int32_t level, int32_t what, double *out, int64_t *count) {
+    return guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        linearize(st);
+        size_t n = st->prec->level_data_d(st, level, what, nullptr);
+        if (count) *count = (int64_t)n;
+        if (out) {
+            DBuf<double> tmp(n);
+            st->prec->level_data_d(st, level, what, tmp.p);
+            OT_HIP(hipMemcpyAsync(out, tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+            OT_HIP(hipStreamSynchronize(st->stream));
+        }
+    });
+}
+
+int otbb_debug_vcycle(ot_state *st, const double *b, double *x) {
+    return dbg_vec(st, b, st ? st->nphi : 0, x, st ? st->nphi : 0,
+                   [&](const double *a, double *o) { st->prec->vcycle_d(st, a, o); });
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+"""Host-side checks of the C-ABI library (no GPU): exported symbols, option
+defaults, mesh validation error codes, and the C++ structured mesh generator
+against the oracle's mesh (bit-exact integer data)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import otinputs
+from oracle.mesh import structured_mesh, cartesian_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    ot = pytest.importorskip("paper_2209_00315_amd")
+    try:
+        return ot, ot.lib()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+def _declared(header):
+    txt = open(os.path.join(ROOT, "include", header)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ot|otbb)_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    ot, L = _lib()
+    names = _declared("otbb.h") + _declared("otbb_debug.h")
+    assert "ot_solve" in names and "ot_apply_schur_prec" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_option_defaults():
+    ot, _ = _lib()
+    o = ot.options()
+    assert (o.tol, o.eps_out, o.eps_in_S) == (1e-6, 1e-5, 1e-1)
+    assert (o.mu0, o.mu_factor, o.frac_to_boundary) == (1.0, 0.2, 0.99)
+    assert (o.max_fgmres, o.max_inner, o.max_newton) == (400, 200, 20)
+    assert o.precision == ot.OT_MIXED and o.mem_kind == ot.OT_HOST
+
+
+def _arrays(n, cart):
+    ot, L = _lib()
+    sz = (C.c_int32 * 8)()
+    assert L.otbb_debug_structured_sizes(n, cart, sz) == 0
+    nf, nc, ne, nce, nov, nlev, ncol, wf = list(sz)
+    fe_cell = np.zeros(2 * ne, np.int32)
+    fe_rho = np.zeros(2 * ne, np.int32)
+    fe_len, fe_dist, fe_lam = np.zeros(ne), np.zeros(ne), np.zeros(ne)
+    ov_f, ov_c, ov_a = np.zeros(nov, np.int32), np.zeros(nov, np.int32), np.zeros(nov)
+    ce_cell = np.zeros(2 * nce, np.int32)
+    ce_len, ce_dist = np.zeros(nce), np.zeros(nce)
+    color = np.zeros(nc, np.int32)
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    assert L.otbb_debug_structured_arrays(n, cart, ip(fe_cell), ip(fe_rho), dp(fe_len), dp(fe_dist), dp(fe_lam),
+                                          ip(ov_f), ip(ov_c), dp(ov_a), ip(ce_cell), dp(ce_len), dp(ce_dist),
+                                          ip(color)) == 0
+    return dict(nf=nf, nc=nc, ne=ne, nce=nce, nlev=nlev, ncol=ncol, fe_cell=fe_cell.reshape(-1, 2),
+                fe_rho=fe_rho.reshape(-1, 2), fe_len=fe_len, fe_dist=fe_dist, fe_lam=fe_lam, ov_f=ov_f,
+                ov_c=ov_c, ov_a=ov_a, ce_cell=ce_cell.reshape(-1, 2), ce_len=ce_len, ce_dist=ce_dist,
+                color=color)
+
+
+@pytest.mark.parametrize("n,cart", [(2, 0), (4, 0), (16, 0), (6, 1), (8, 1)])
+def test_cpp_mesh_matches_oracle_mesh(n, cart):
+    d = _arrays(n, cart)
+    m = (cartesian_mesh if cart else structured_mesh)(n)
+    assert (d["nf"], d["nc"], d["ne"], d["nce"]) == (m.n_fine, m.n_coarse, m.n_fedge, m.n_cedge)
+    key = lambda K, L, rK, rL: sorted(zip(K.tolist(), L.tolist(), rK.tolist(), rL.tolist()))
+    assert key(d["fe_cell"][:, 0], d["fe_cell"][:, 1], d["fe_rho"][:, 0], d["fe_rho"][:, 1]) == \
+        key(m.fe_K, m.fe_L, m.fe_rK, m.fe_rL)
+    assert np.array_equal(np.sort(d["fe_len"]), np.sort(m.fe_len))
+    ov1 = sorted(zip(d["ov_f"].tolist(), d["ov_c"].tolist(), d["ov_a"].tolist()))
+    ov2 = sorted(zip(m.ov_fine.tolist(), m.ov_coarse.tolist(), m.ov_area.tolist()))
+    assert ov1 == ov2
+    ce1 = sorted(zip(np.minimum(*d["ce_cell"].T).tolist(), np.maximum(*d["ce_cell"].T).tolist(),
+                     np.round(d["ce_dist"], 15).tolist()))
+    ce2 = sorted(zip(np.minimum(m.ce_i, m.ce_j).tolist(), np.maximum(m.ce_i, m.ce_j).tolist(),
+                     np.round(m.ce_dist, 15).tolist()))
+    assert ce1 == ce2
+
+
+def test_coloring_separates_coupled_cells():
+    """Cells of one color never share a fine cell within one fine edge of
+    their overlaps (the stencil of the pseudo-Schur operator)."""
+    n = 16
+    d = _arrays(n, 0)
+    m = structured_mesh(n)
+    col = d["color"]
+    nf = m.n_fine
+    adj = [set([i]) for i in range(nf)]
+    for K, L in zip(m.fe_K, m.fe_L):
+        adj[K].add(L)
+        adj[L].add(K)
+    touch = [set() for _ in range(m.n_coarse)]          # fine cells near coarse j
+    for i, j in zip(m.ov_fine, m.ov_coarse):
+        touch[j] |= adj[i]
+    reach = [set() for _ in range(nf)]                  # coarse cells read at fine i
+    for i, j in zip(m.ov_fine, m.ov_coarse):
+        reach[i].add(j)
+    for e in range(m.n_fedge):
+        for i in (m.fe_K[e], m.fe_L[e]):
+            reach[i] |= {m.fe_rK[e], m.fe_rL[e]}
+    for j in range(m.n_coarse):
+        for i in touch[j]:
+            for c in reach[i]:
+                if c != j:
+                    assert col[c] != col[j]
+
+
+def _desc_args(d):
+    ot, L = _lib()
+    from paper_2209_00315_amd import _lib as LL
+    keep = []
+
+    def dd(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        keep.append(a)
+        return a.ctypes.data_as(LL.dptr)
+
+    def ii(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+        keep.append(a)
+        return a.ctypes.data_as(LL.iptr)
+
+    desc = LL.MeshDesc(
+        n_fine=len(d["fine_area"]), n_coarse=len(d["coarse_area"]), fine_area=dd(d["fine_area"]),
+        coarse_area=dd(d["coarse_area"]), n_overlap=len(d["ov_area"]), ov_fine=ii(d["ov_fine"]),
+        ov_coarse=ii(d["ov_coarse"]), ov_area=dd(d["ov_area"]), n_fedge=len(d["fe_len"]),
+        fe_cell=ii(d["fe_cell"]), fe_rho=ii(d["fe_rho"]), fe_len=dd(d["fe_len"]), fe_dist=dd(d["fe_dist"]),
+        fe_lambda=dd(d["fe_lambda"]), n_cedge=len(d["ce_len"]), ce_cell=ii(d["ce_cell"]),
+        ce_len=dd(d["ce_len"]), ce_dist=dd(d["ce_dist"]), ce_lambda=dd(d["ce_lambda"]))
+    return L, desc, keep
+
+
+def test_desc_validation_codes():
+    ot, _ = _lib()
+    base = otinputs.random_mesh_arrays(40, 12, seed=1)
+    L, desc, keep = _desc_args(base)
+    assert L.otbb_debug_validate_desc(C.byref(desc)) == 0
+    bad_cases = [
+        ("fine_area", lambda d: d["fine_area"].__setitem__(0, -1.0), ot.OT_EMESH),
+        ("fe_dist", lambda d: d["fe_dist"].__setitem__(3, 0.0), ot.OT_EMESH),
+        ("fe_lambda", lambda d: d["fe_lambda"].__setitem__(2, 1.5), ot.OT_EMESH),
+        ("ov_area", lambda d: d["ov_area"].__setitem__(0, d["ov_area"][0] * 2), ot.OT_EMESH),
+        ("fe_cell", lambda d: d["fe_cell"].__setitem__(0, 10 ** 6), ot.OT_EMESH),
+        ("fe_rho", lambda d: d["fe_rho"].__setitem__(1, -3), ot.OT_EMESH),
+    ]
+    for name, mut, code in bad_cases:
+        d = {k: np.array(v, copy=True) for k, v in base.items()}
+        mut(d)
+        L, desc, keep = _desc_args(d)
+        assert L.otbb_debug_validate_desc(C.byref(desc)) == code, name
+    # ot_mesh_create rejects the same descriptions before any device work
+    d = {k: np.array(v, copy=True) for k, v in base.items()}
+    d["fe_dist"][0] = -1.0
+    L, desc, keep = _desc_args(d)
+    h = C.c_void_p()
+    assert L.ot_mesh_create(C.byref(desc), C.byref(h)) == ot.OT_EMESH
+    assert b"distance" in L.ot_last_error()
+    assert L.ot_mesh_create(None, C.byref(h)) == ot.OT_EINVAL
+    assert L.ot_mesh_create_structured(3, 0, C.byref(h)) != 0      # odd n on the triangle grid
+
+
+def test_random_mesh_is_valid_for_oracle():
+    from oracle.mesh import mesh_from_arrays
+    from oracle.operators import Operators
+    d = otinputs.random_mesh_arrays(60, 20, seed=3)
+    o = Operators(mesh_from_arrays(d))
+    assert np.allclose(np.asarray(o.Om.sum(1)).ravel(), o.a)
+    assert np.allclose(np.asarray(o.Om.sum(0)).ravel(), o.ac)
