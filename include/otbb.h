@@ -100,15 +100,21 @@ typedef struct {
  * Solver options; ot_options_default() fills the paper's settings:
  *  tol 1e-6 (Newton, absolute Euclidean norm of (F_phi; F_rho; F_s - mu),
  *  Sec. 2.4), eps_out 1e-5 (FGMRES, relative to |(f;g;h)|, Sec. 3.1),
- *  eps_in_S 1e-1 (pseudo-Schur inner solve, Sec. 4.4.4), eps_in_A 1e-2
- *  (Laplacian inner solves; the paper's 5e-2 was tuned for its AMG),
+ *  eps_in_S 1e-1 (pseudo-Schur inner solve, Sec. 4.4.4), eps_in_A 1e-4
+ *  (Laplacian inner solves: PCG stops on the residual, which at the
+ *  paper's 5e-2 leaves low-energy error that the outer FGMRES pays for
+ *  once mu is small),
  *  mu0 1, mu_factor 0.2, step fraction 0.99, caps 400 FGMRES / 200 inner /
- *  20 Newton, restart 40, OT_MIXED, OT_HOST, null stream.
+ *  20 Newton, restart 100, inner restart 30, accept_relres 1e-2, OT_MIXED,
+ *  OT_HOST, null stream.
  */
 typedef struct {
     double tol, eps_out, eps_in_S, eps_in_A;
     double mu0, mu_factor, frac_to_boundary;
     double final_tol;        /* <= 0: use tol for the last mu as well       */
+    double accept_relres;    /* a Newton step whose FGMRES stopped at the cap
+                                is still taken when its relative residual is
+                                below this value (counted as a failure)     */
     int32_t max_fgmres, restart, max_inner, max_newton, inner_restart;
     int32_t precision, mem_kind;
     int32_t verbose;
@@ -123,6 +129,7 @@ typedef struct {
     double seconds_total, seconds_linear, seconds_setup;
     double final_residual, mu;
     double cost, dual, gap;
+    double last_relres;      /* FGMRES relative residual of the last system  */
 } ot_stats;
 
 void ot_options_default(ot_options *opt);

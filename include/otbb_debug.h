@@ -34,6 +34,11 @@ int otbb_debug_structured_arrays(int32_t n, int32_t cartesian, int32_t *fe_cell,
  * before its device upload. */
 int otbb_debug_validate_desc(const ot_mesh_desc *desc);
 
+/* Pseudo-Schur multigrid hierarchy of that structured mesh: out[0] = number
+ * of levels, then (cells, stencil width, colours) per level, up to cap
+ * entries in total. */
+int otbb_debug_schur_levels(int32_t n, int32_t cartesian, int32_t *out, int32_t cap);
+
 /*
  * Components of the BB preconditioner at the state's current linearisation
  * (built on first use), host pointers in and out, FP64 at the interface and

@@ -323,8 +323,8 @@ def _run_ipm(st, tol, mu_factor=None):
                 break
             if it == o.max_newton:
                 break
-            rc, _, _ = st.newton_step(raise_on_error=False)
-            if rc not in (OT_OK, OT_ELINSOLVE):
+            rc, stats, _ = st.newton_step(raise_on_error=False)
+            if rc != OT_OK and not (rc == OT_ELINSOLVE and stats.last_relres <= o.accept_relres):
                 return rc
         if not ok:
             return OT_ENEWTON

@@ -29,7 +29,7 @@ class Options(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("eps_out", C.c_double), ("eps_in_S", C.c_double), ("eps_in_A", C.c_double),
         ("mu0", C.c_double), ("mu_factor", C.c_double), ("frac_to_boundary", C.c_double),
-        ("final_tol", C.c_double),
+        ("final_tol", C.c_double), ("accept_relres", C.c_double),
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
         ("max_newton", C.c_int32), ("inner_restart", C.c_int32),
         ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
@@ -45,6 +45,7 @@ class Stats(C.Structure):
         ("seconds_total", C.c_double), ("seconds_linear", C.c_double), ("seconds_setup", C.c_double),
         ("final_residual", C.c_double), ("mu", C.c_double),
         ("cost", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
+        ("last_relres", C.c_double),
     ]
 
     def as_dict(self):
@@ -95,6 +96,7 @@ SIGNATURES = {
     "otbb_debug_structured_arrays": (C.c_int, [C.c_int32, C.c_int32, iptr, iptr, dptr, dptr, dptr,
                                                iptr, iptr, dptr, iptr, dptr, dptr, iptr]),
     "otbb_debug_validate_desc": (C.c_int, [C.POINTER(MeshDesc)]),
+    "otbb_debug_schur_levels": (C.c_int, [C.c_int32, C.c_int32, iptr, C.c_int32]),
     "otbb_debug_schur_apply": (C.c_int, [C.c_void_p, dptr, dptr]),
     "otbb_debug_schur_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
     "otbb_debug_tri_diagonals": (C.c_int, [C.c_void_p, dptr, dptr, dptr]),

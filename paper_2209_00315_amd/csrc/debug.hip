@@ -97,3 +97,19 @@ int otbb_debug_validate_desc(const ot_mesh_desc *d) {
 }
 
 }  // extern "C"
+
+extern "C" int otbb_debug_schur_levels(int32_t n, int32_t cartesian, int32_t *out, int32_t cap) {
+    return guard_dbg([&] {
+        OT_REQUIRE(out && cap >= 1, OT_EINVAL, "null argument");
+        MeshHost h;
+        structured_desc(n, cartesian != 0, h);
+        derive_host_only(h);
+        int nl = (int)h.slevels.size();
+        out[0] = nl;
+        for (int l = 0; l < nl && 1 + 3 * l + 2 < cap; ++l) {
+            out[1 + 3 * l] = h.slevels[l].n;
+            out[2 + 3 * l] = h.slevels[l].w;
+            out[3 + 3 * l] = h.slevels[l].ncolor;
+        }
+    });
+}

@@ -513,22 +513,55 @@ __global__ void k_tri_factor(int nc, int K, const double *__restrict__ d0, const
     }
 }
 
+// Forward/backward substitution along time for every coarse cell.  Loads of
+// a chunk of TC levels are issued before the dependent arithmetic so that
+// each thread keeps TC memory requests in flight (one thread per cell gives
+// only nc threads, so latency hiding has to come from within the thread).
 template <typename T>
 __global__ void k_tri_solve(int nc, int K, const T *__restrict__ inv_dd, const T *__restrict__ lm,
                             const T *__restrict__ up, const T *__restrict__ r, T *__restrict__ x) {
+    constexpr int TC = 8;
     const int j = blockIdx.x * BS + threadIdx.x;
     if (j >= nc) return;
     double y = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const size_t q = (size_t)k * nc + j;
-        y = (double)r[q] - (double)lm[q] * y;
-        x[q] = (T)y;
+    for (int k0 = 0; k0 < K; k0 += TC) {
+        double rr[TC], ll[TC];
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+            const int k = k0 + t;
+            const size_t q = (size_t)k * nc + j;
+            rr[t] = k < K ? (double)r[q] : 0.0;
+            ll[t] = k < K ? (double)lm[q] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+            const int k = k0 + t;
+            if (k < K) {
+                y = rr[t] - ll[t] * y;
+                x[(size_t)k * nc + j] = (T)y;
+            }
+        }
     }
     double xn = 0.0;
-    for (int k = K - 1; k >= 0; --k) {
-        const size_t q = (size_t)k * nc + j;
-        xn = ((double)x[q] - (double)up[q] * xn) * (double)inv_dd[q];
-        x[q] = (T)xn;
+    const int kl = ((K + TC - 1) / TC) * TC;
+    for (int k0 = kl - TC; k0 >= 0; k0 -= TC) {
+        double yy[TC], uu[TC], dd[TC];
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+            const int k = k0 + t;
+            const size_t q = (size_t)k * nc + j;
+            yy[t] = k < K ? (double)x[q] : 0.0;
+            uu[t] = k < K ? (double)up[q] : 0.0;
+            dd[t] = k < K ? (double)inv_dd[q] : 0.0;
+        }
+#pragma unroll
+        for (int t = TC - 1; t >= 0; --t) {
+            const int k = k0 + t;
+            if (k < K) {
+                xn = (yy[t] - uu[t] * xn) * dd[t];
+                x[(size_t)k * nc + j] = (T)xn;
+            }
+        }
     }
 }
 
@@ -689,11 +722,11 @@ __global__ void k_mg_restrict(LevelView L, int n_next, const int *__restrict__ p
 
 template <typename T>
 __global__ void k_mg_prolong(int n, int n_next, const int *__restrict__ agg, const T *__restrict__ xc,
-                             T *__restrict__ x) {
+                             T *__restrict__ x, double alpha) {
     const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     if (i >= n) return;
     const size_t q = (size_t)k * n + i;
-    x[q] = (T)((double)x[q] + (double)xc[(size_t)k * n_next + agg[i]]);
+    x[q] = (T)((double)x[q] + alpha * (double)xc[(size_t)k * n_next + agg[i]]);
 }
 
 // per-slice PCG updates with host-provided per-slice scalars in alpha/beta
@@ -714,6 +747,101 @@ __global__ void k_pcg_p(int n, const double *__restrict__ beta, const T *__restr
     if (i >= n) return;
     const size_t o = (size_t)k * n + i;
     p[o] = (T)((double)z[o] + beta[k] * (double)p[o]);
+}
+
+// y = x * d (inv = 0) or y = x / d (inv = 1), d a per-entry FP64 scale
+template <typename T>
+__global__ void k_dscale(size_t n, const double *__restrict__ d, int inv, const T *__restrict__ x, T *__restrict__ y) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        const double di = d[i];
+        const double f = inv ? (di != 0.0 ? 1.0 / di : 1.0) : di;
+        y[i] = (T)((double)x[i] * f);
+    }
+}
+
+// ------------------------------------------- pseudo-Schur multigrid levels
+// Level l >= 1 stores its Galerkin operator as v[((d * w + slot) * K + k) * n + a],
+// d = time offset + 1 in {0, 1, 2}, slot over the ELL stencil nbr (slot 0 = self).
+struct SLevelView {
+    int n, w;
+    const int *nbr;
+};
+
+// probe at level l-1 for the colours of level l: 1 at (k, j) with k % 3 == tc
+// and the colour of j's aggregate equal to c
+template <typename T>
+__global__ void k_sprobe(int n_prev, const int *__restrict__ agg, const int *__restrict__ color, int tc, int c,
+                         T *__restrict__ p) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j < n_prev) p[(size_t)k * n_prev + j] = (T)((k % 3 == tc && color[agg[j]] == c) ? 1.0 : 0.0);
+}
+
+// R[k][a] = sum over the members j of aggregate a of r[k][j]
+template <typename T>
+__global__ void k_srestrict(int n_next, int n, const int *__restrict__ ptr, const int *__restrict__ idx,
+                            const T *__restrict__ r, T *__restrict__ R) {
+    const int a = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (a >= n_next) return;
+    double v = 0.0;
+    for (int p = ptr[a]; p < ptr[a + 1]; ++p) v += (double)r[(size_t)k * n + idx[p]];
+    R[(size_t)k * n_next + a] = (T)v;
+}
+
+// scatter a restricted probe response into the stencil slot of the
+// colour-c neighbour, at the single time offset whose level is in class tc
+template <typename T>
+__global__ void k_sscatter(SLevelView L, int K, const int *__restrict__ slot_of, int tc, int c,
+                           const T *__restrict__ R, T *__restrict__ v) {
+    const int a = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (a >= L.n) return;
+    const int slot = slot_of[(size_t)c * L.n + a];
+    if (slot < 0) return;
+    for (int d = -1; d <= 1; ++d) {
+        const int kk = k + d;
+        if (kk < 0 || kk >= K || kk % 3 != tc) continue;
+        v[(((size_t)(d + 1) * L.w + slot) * K + k) * L.n + a] = R[(size_t)k * L.n + a];
+    }
+}
+
+// y = S x, or y = b - S x when b is given
+template <typename T>
+__global__ void k_sspmv(SLevelView L, int K, const T *__restrict__ v, const T *__restrict__ x,
+                        const T *__restrict__ b, T *__restrict__ y) {
+    const int a = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (a >= L.n) return;
+    double acc = 0.0;
+    for (int s = 0; s < L.w; ++s) {
+        const int nb = L.nbr[(size_t)s * L.n + a];
+        if (nb < 0) break;
+        for (int d = -1; d <= 1; ++d) {
+            const int kk = k + d;
+            if (kk < 0 || kk >= K) continue;
+            acc += (double)v[(((size_t)(d + 1) * L.w + s) * K + k) * L.n + a] * (double)x[(size_t)kk * L.n + nb];
+        }
+    }
+    const size_t q = (size_t)k * L.n + a;
+    y[q] = (T)(b ? (double)b[q] - acc : acc);
+}
+
+// time diagonals of a level's own stencil slot
+template <typename T>
+__global__ void k_sdiag(SLevelView L, int K, const T *__restrict__ v, double *__restrict__ d0,
+                        double *__restrict__ dl, double *__restrict__ du) {
+    const int a = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (a >= L.n) return;
+    const size_t q = (size_t)k * L.n + a;
+    dl[q] = (double)v[(((size_t)0 * L.w + 0) * K + k) * L.n + a];
+    d0[q] = (double)v[(((size_t)1 * L.w + 0) * K + k) * L.n + a];
+    du[q] = (double)v[(((size_t)2 * L.w + 0) * K + k) * L.n + a];
+}
+
+template <typename T>
+__global__ void k_sprolong(int n, int n_next, const int *__restrict__ agg, const T *__restrict__ xc,
+                           T *__restrict__ x) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= n) return;
+    const size_t q = (size_t)k * n + j;
+    x[q] = (T)((double)x[q] + (double)xc[(size_t)k * n_next + agg[j]]);
 }
 
 // ----------------------------------------------------- Newton step pieces

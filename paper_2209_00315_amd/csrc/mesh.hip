@@ -318,6 +318,8 @@ static void color_coarse(MeshHost &h) {
     for (int e = 0; e < h.nce; ++e) { cpl[h.ceI[e]].insert(h.ceJ[e]); cpl[h.ceJ[e]].insert(h.ceI[e]); }
     for (int j = 0; j < h.nc; ++j)
         for (int c : cpl[j]) cpl[c].insert(j);        // symmetric closure
+    h.cpl.assign(h.nc, {});
+    for (int j = 0; j < h.nc; ++j) h.cpl[j].assign(cpl[j].begin(), cpl[j].end());
     h.color.assign(h.nc, -1);
     h.ncolor = 0;
     std::vector<int> mark;
@@ -328,6 +330,90 @@ static void color_coarse(MeshHost &h) {
         while (mark[col]) ++col;
         h.color[j] = col;
         h.ncolor = std::max(h.ncolor, col + 1);
+    }
+}
+
+// Pseudo-Schur multigrid hierarchy over the density cells.  Aggregation
+// follows the coarse edge graph (root plus neighbours, then leftovers join
+// the aggregate they touch most); the stencil of level l+1 is the union of
+// the stencils of the member cells; a distance-2 coloring of every coarse
+// level lets one probe per (time class, colour) recover its Galerkin
+// operator exactly.
+static void build_schur_hierarchy(MeshHost &h) {
+    h.slevels.clear();
+    std::vector<std::vector<int>> st(h.nc);
+    for (int j = 0; j < h.nc; ++j) {
+        st[j].push_back(j);
+        for (int c : h.cpl[j]) st[j].push_back(c);
+    }
+    std::vector<int> ei = h.ceI, ej = h.ceJ;
+    int n = h.nc;
+    for (int lvl = 0; lvl < 16; ++lvl) {
+        SLevelHost L;
+        L.n = n;
+        L.w = 1;
+        for (auto &r : st) L.w = std::max(L.w, (int)r.size());
+        L.nbr.assign((size_t)L.w * n, -1);
+        for (int a = 0; a < n; ++a)
+            for (size_t t = 0; t < st[a].size(); ++t) L.nbr[t * n + a] = st[a][t];
+        if (lvl > 0) {
+            // distance-2 coloring: the columns of every row get distinct colours
+            L.color.assign(n, -1);
+            std::vector<int> mark;
+            for (int b = 0; b < n; ++b) {
+                mark.assign(L.ncolor + 1, 0);
+                for (int a : st[b])
+                    for (int c : st[a])
+                        if (L.color[c] >= 0 && L.color[c] <= L.ncolor) mark[L.color[c]] = 1;
+                int col = 0;
+                while (col < (int)mark.size() && mark[col]) ++col;
+                L.color[b] = col;
+                L.ncolor = std::max(L.ncolor, col + 1);
+            }
+            L.slot_of.assign((size_t)L.ncolor * n, -1);
+            for (int a = 0; a < n; ++a)
+                for (size_t t = 0; t < st[a].size(); ++t) {
+                    int &slot = L.slot_of[(size_t)L.color[st[a][t]] * n + a];
+                    OT_REQUIRE(slot < 0, OT_EMESH, "internal: coloring not distance-2");
+                    slot = (int)t;
+                }
+        }
+        bool last = n <= 16;
+        std::vector<int> agg;
+        int nagg = 0;
+        if (!last) {
+            aggregate(n, 0, ei, ej, agg, nagg);
+            if (nagg > (9 * n) / 10 || nagg < 1) last = true;
+        }
+        if (!last) {
+            L.agg = agg;
+            L.mem_ptr.assign(nagg + 1, 0);
+            for (int i = 0; i < n; ++i) L.mem_ptr[agg[i] + 1]++;
+            for (int c = 0; c < nagg; ++c) L.mem_ptr[c + 1] += L.mem_ptr[c];
+            L.mem_idx.assign(n, 0);
+            std::vector<int> pos(L.mem_ptr.begin(), L.mem_ptr.end() - 1);
+            for (int i = 0; i < n; ++i) L.mem_idx[pos[agg[i]]++] = i;
+            // next stencil and aggregation graph
+            std::vector<std::set<int>> ns(nagg);
+            for (int a = 0; a < n; ++a)
+                for (int b : st[a]) ns[agg[a]].insert(agg[b]);
+            std::set<std::pair<int, int>> ne;
+            for (size_t e = 0; e < ei.size(); ++e) {
+                int u = agg[ei[e]], v = agg[ej[e]];
+                if (u != v) ne.insert({std::min(u, v), std::max(u, v)});
+            }
+            std::vector<std::vector<int>> nst(nagg);
+            for (int a = 0; a < nagg; ++a) {
+                nst[a].push_back(a);
+                for (int b : ns[a]) if (b != a) nst[a].push_back(b);
+            }
+            st.swap(nst);
+            ei.clear(); ej.clear();
+            for (auto &pr : ne) { ei.push_back(pr.first); ej.push_back(pr.second); }
+            n = nagg;
+        }
+        h.slevels.push_back(std::move(L));
+        if (last) break;
     }
 }
 
@@ -372,6 +458,7 @@ static void derive(MeshHost &h) {
     }
     build_hierarchy(h);
     color_coarse(h);
+    build_schur_hierarchy(h);
     // Every kernel walks an ELL row until its stop column reads -1 and then
     // gathers through the paired column: check that padding is contiguous
     // and every gathered index is in range before anything reaches a device.
@@ -395,6 +482,16 @@ static void derive(MeshHost &h) {
               ell_ok(h.fo_c, {}, h.wo, h.nf, h.nc, 0) && ell_ok(h.co_f, {}, h.woc, h.nc, h.nf, 0) &&
               ell_ok(h.cr_e, {}, h.wr, h.nc, h.ne, 0) && ell_ok(h.cc_edge, h.cc_nb, h.wcc, h.nc, h.nce, h.nc);
     for (const MGLevelHost &L : h.levels) ok = ok && ell_ok(L.ed, L.nb, L.w, L.n, std::max(L.ne, 1), L.n);
+    for (size_t l = 0; l < h.slevels.size(); ++l) {
+        const SLevelHost &L = h.slevels[l];
+        ok = ok && ell_ok(L.nbr, {}, L.w, L.n, L.n, 0);
+        for (int a = 0; a < L.n; ++a) ok = ok && L.nbr[a] == a;             // slot 0 is the cell itself
+        if (!L.agg.empty()) {
+            const int nn = (int)L.mem_ptr.size() - 1;
+            for (int a : L.agg) ok = ok && a >= 0 && a < nn;
+            ok = ok && l + 1 < h.slevels.size() && h.slevels[l + 1].n == nn;
+        }
+    }
     OT_REQUIRE(ok, OT_EMESH, "internal: inconsistent ELL index structure");
 }
 
@@ -428,6 +525,19 @@ void mesh_finalize(ot_mesh *m) {
     m->fo_c.upload(h.fo_c, s); m->co_f.upload(h.co_f, s); m->cr_e.upload(h.cr_e, s);
     m->cc_edge.upload(h.cc_edge, s); m->cc_nb.upload(h.cc_nb, s);
     m->color.upload(h.color, s);
+    m->slv.clear();
+    for (size_t l = 0; l < h.slevels.size(); ++l) {
+        const SLevelHost &L = h.slevels[l];
+        SLevelDev D;
+        D.n = L.n; D.w = L.w; D.ncolor = L.ncolor;
+        D.nbr.upload(L.nbr, s);
+        if (!L.color.empty()) { D.color.upload(L.color, s); D.slot_of.upload(L.slot_of, s); }
+        if (!L.agg.empty()) {
+            D.n_next = (int)L.mem_ptr.size() - 1;
+            D.agg.upload(L.agg, s); D.mem_ptr.upload(L.mem_ptr, s); D.mem_idx.upload(L.mem_idx, s);
+        }
+        m->slv.push_back(std::move(D));
+    }
     m->lv.clear();
     for (size_t l = 0; l < h.levels.size(); ++l) {
         const MGLevelHost &L = h.levels[l];

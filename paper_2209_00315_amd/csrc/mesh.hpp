@@ -22,6 +22,25 @@ struct MGLevelDev {
     DBuf<int> nb, ed, agg, mem_ptr, mem_idx, cedge_ptr, cedge_idx;
 };
 
+// One level of the aggregation hierarchy of the coarse (density) cells used
+// by the multigrid preconditioner of the pseudo-Schur system.  Level 0 is
+// the density cells themselves (operator applied matrix-free); level l >= 1
+// holds a Galerkin operator assembled by probing, stored per time offset
+// (-1, 0, +1) in ELL form over the level's stencil.
+struct SLevelHost {
+    int n = 0, w = 0;                  // cells, stencil width (slot 0 = self)
+    std::vector<int> nbr;              // [w * n] col-major, -1 pads
+    int ncolor = 0;                    // distance-2 coloring over the stencil
+    std::vector<int> color;
+    std::vector<int> slot_of;          // [ncolor * n]: slot of the colour-c neighbour, -1
+    std::vector<int> agg, mem_ptr, mem_idx;   // to the next level (empty at the last)
+};
+
+struct SLevelDev {
+    int n = 0, w = 0, ncolor = 0, n_next = 0;
+    DBuf<int> nbr, color, slot_of, agg, mem_ptr, mem_idx;
+};
+
 // Host copy of the description plus every derived index structure.
 struct MeshHost {
     int nf = 0, nc = 0, ne = 0, nce = 0;
@@ -50,6 +69,8 @@ struct MeshHost {
     std::vector<MGLevelHost> levels;
     int ncolor = 0;                    // distance coloring of the coarse cells
     std::vector<int> color;            // for probing the pseudo-Schur diagonal
+    std::vector<std::vector<int>> cpl; // pseudo-Schur stencil of each coarse cell (no self)
+    std::vector<SLevelHost> slevels;   // pseudo-Schur multigrid hierarchy
 };
 
 }  // namespace otbb
@@ -63,6 +84,7 @@ struct ot_mesh {
     otbb::DBuf<int> eK, eL, erK, erL, ceI, ceJ, cf_edge, cf_nb, fo_c, co_f, cr_e, cc_edge, cc_nb;
     otbb::DBuf<int> color;
     std::vector<otbb::MGLevelDev> lv;
+    std::vector<otbb::SLevelDev> slv;
     double area = 0.0;                 // |Omega| = sum of coarse areas
 };
 
