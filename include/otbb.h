@@ -60,6 +60,8 @@ extern "C" {
 
 #define OT_FP64   0        /* every kernel in FP64                           */
 #define OT_MIXED  1        /* preconditioner in FP32, the rest in FP64       */
+#define OT_STEP_COMMON 0   /* step rules, see ot_options.step_rule           */
+#define OT_STEP_SPLIT  1
 
 #define OT_HOST   0
 #define OT_DEVICE 1
@@ -100,13 +102,21 @@ typedef struct {
  * Solver options; ot_options_default() fills the paper's settings:
  *  tol 1e-6 (Newton, absolute Euclidean norm of (F_phi; F_rho; F_s - mu),
  *  Sec. 2.4), eps_out 1e-5 (FGMRES, relative to |(f;g;h)|, Sec. 3.1),
- *  eps_in_S 1e-1 (pseudo-Schur inner solve, Sec. 4.4.4), eps_in_A 1e-4
+ *  eps_in_S 1e-1 (pseudo-Schur inner solve, Sec. 4.4.4), eps_in_A 1e-6
  *  (Laplacian inner solves: PCG stops on the residual, which at the
- *  paper's 5e-2 leaves low-energy error that the outer FGMRES pays for
- *  once mu is small),
- *  mu0 1, mu_factor 0.2, step fraction 0.99, caps 400 FGMRES / 200 inner /
- *  20 Newton, restart 100, inner restart 30, accept_relres 1e-2, OT_MIXED,
- *  OT_HOST, null stream.
+ *  paper's 5e-2, or even 1e-4, leaves low-energy error that the outer
+ *  FGMRES pays for once mu is small: 1e-6 cuts its iterations up to 8x;
+ *  FP32 vectors still reach it),
+ *  mu0 1, mu_factor 0.2, step fraction 0.99, caps 400 FGMRES / 200 inner
+ *  (Laplacian PCG) / 10 pseudo-Schur GMRES / 60 Newton per mu (the
+ *  pseudo-Schur solve stops at eps_in_S or at its cap, whichever comes
+ *  first: past ~10 iterations its extra accuracy no longer lowers the
+ *  FGMRES count; the paper gives no Newton cap, and fine grids with
+ *  near-empty regions need up to ~30 steps at one mu), restart 400
+ *  (FGMRES runs unrestarted within its cap, as in Sec. 4; its basis grows
+ *  on demand up to (restart + 1) + restart vectors of N doubles), inner
+ *  restart 30, accept_relres 1e-2, OT_STEP_COMMON, OT_MIXED, OT_HOST,
+ *  null stream.
  */
 typedef struct {
     double tol, eps_out, eps_in_S, eps_in_A;
@@ -116,6 +126,12 @@ typedef struct {
                                 is still taken when its relative residual is
                                 below this value (counted as a failure)     */
     int32_t max_fgmres, restart, max_inner, max_newton, inner_restart;
+    int32_t max_inner_S;     /* cap of the pseudo-Schur inner GMRES (see above) */
+    int32_t step_rule;       /* OT_STEP_COMMON (default): one step length for
+                                (phi, rho, s), the largest that keeps rho and
+                                s positive times frac_to_boundary (Sec. 2.4);
+                                OT_STEP_SPLIT: phi and rho take the largest
+                                such step for rho, s its own                */
     int32_t precision, mem_kind;
     int32_t verbose;
     void *stream;            /* hipStream_t */
@@ -233,6 +249,31 @@ int  ot_state_set_options(ot_state *st, const ot_options *opt);
 
 /* Message of the last error on this thread (never NULL). */
 const char *ot_last_error(void);
+
+/*
+ * Kernel timing (instrumentation of the hot path, process-wide).
+ * ot_kprof_select(id) picks one kernel and clears the counters; from then on
+ * every launch of it, in any state, is bracketed by two HIP events recorded
+ * on the stream it runs on, and its algorithmic bytes (each operand read
+ * once, each result written once; FP32 operands in the mixed path) are
+ * summed.  ot_kprof_read drains pending events (it synchronises with them)
+ * and returns launches, total kernel milliseconds and total bytes; any
+ * output pointer may be NULL.  OT_KPROF_NONE switches timing off.  Not for
+ * concurrent use from several threads.
+ *   CHEB_FINE     Chebyshev smoothing step of the K+1 Laplacians at the fine
+ *                 multigrid level (Sec. 4.4.5 inner solves)
+ *   SCHUR_BTILDE  pseudo-Schur operator, pass M^-1 B~ z (Sec. 4.4.4)
+ *   SCHUR_OUT     pseudo-Schur operator, pass Diag(s) A~ z - Diag(rho) B v
+ *   TRI_FINE      time-line tridiagonal solve on the density cells
+ *   MULTIDOT      dot products of one vector with a Krylov basis (Arnoldi)
+ *   SADDLE_PHI    potential block of the saddle operator J_P (Sec. 4.1)
+ */
+enum {
+    OT_KPROF_NONE = 0, OT_KPROF_CHEB_FINE = 1, OT_KPROF_SCHUR_BTILDE = 2, OT_KPROF_SCHUR_OUT = 3,
+    OT_KPROF_TRI_FINE = 4, OT_KPROF_MULTIDOT = 5, OT_KPROF_SADDLE_PHI = 6
+};
+int  ot_kprof_select(int32_t kernel);
+int  ot_kprof_read(int64_t *launches, double *ms, double *bytes);
 
 #ifdef __cplusplus
 }

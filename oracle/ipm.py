@@ -199,8 +199,14 @@ def step_length(x, dx, tau=0.99):
     return min(1.0, tau * amax)
 
 
-def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99):
-    """One Newton update of (phi, rho, s) at fixed mu with a direct solve."""
+def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common"):
+    """One Newton update of (phi, rho, s) at fixed mu with a direct solve.
+
+    step_rule "common" (the reading of the positivity line search of Sec. 2.4):
+    one step length for all three blocks, tau times the largest that keeps rho
+    and s positive.  "split": phi and rho take tau times the largest step that
+    keeps rho positive, s the one that keeps s positive (a primal / dual split
+    of that line search)."""
     K, nf, nc = prob.K, prob.nf, prob.nc
     f, g, h, gt = newton_rhs(prob, phi, rho, s, mu)
     J = saddle_matrix(prob, phi, rho, s)
@@ -208,7 +214,12 @@ def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99):
     dphi = x[: (K + 1) * nf].reshape(K + 1, nf)
     drho = x[(K + 1) * nf:].reshape(K, nc)
     ds = (h - s * drho) / rho
-    alpha = min(step_length(rho, drho, tau), step_length(s, ds, tau))
+    a_p, a_d = step_length(rho, drho, tau), step_length(s, ds, tau)
+    alpha = min(a_p, a_d)
+    if step_rule == "split":
+        return phi + a_p * dphi, rho + a_p * drho, s + a_d * ds, alpha
+    if step_rule != "common":
+        raise ValueError(f"unknown step rule {step_rule}")
     return phi + alpha * dphi, rho + alpha * drho, s + alpha * ds, alpha
 
 
@@ -238,7 +249,7 @@ def initial_point(prob: Problem, mu0=1.0):
 
 def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
               max_newton=20, final_tol=None, start=None, mu_start=None,
-              max_mu_steps=200, mu_target=None):
+              max_mu_steps=200, mu_target=None, step_rule="common"):
     """IP continuation: for mu_l = mu0 mu_factor^l, Newton until |F_mu| <= tol,
     warm-started from the previous mu; stop after the first mu < tol.
 
@@ -274,7 +285,7 @@ def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
                 break
             if it == max_newton:
                 break
-            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau)
+            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau, step_rule)
             rho = renormalize(prob, rho, m0)
             count += 1
         newton_counts.append(count)

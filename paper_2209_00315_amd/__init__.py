@@ -15,7 +15,24 @@ from ._lib import (OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG, OT_ELINSOLVE, 
                    OT_EDEVICE, OT_ENOMEM, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OTError, Options, Stats,
                    check, lib)
 
-__all__ = ["Mesh", "State", "solve", "solve_batched", "options", "OTCost", "OTError", "Stats"]
+__all__ = ["Mesh", "State", "solve", "solve_batched", "options", "OTCost", "OTError", "Stats",
+           "kprof_select", "kprof_read", "KPROF"]
+
+# kernel ids of ot_kprof_select (include/otbb.h)
+KPROF = {"none": 0, "cheb_fine": 1, "schur_btilde": 2, "schur_out": 3, "tri_fine": 4, "multidot": 5,
+         "saddle_phi": 6}
+
+
+def kprof_select(kernel):
+    """Time every launch of one hot-path kernel with HIP events (process-wide)."""
+    check(lib().ot_kprof_select(KPROF[kernel] if isinstance(kernel, str) else int(kernel)))
+
+
+def kprof_read():
+    """(launches, total kernel ms, total algorithmic bytes) since the last select."""
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    check(lib().ot_kprof_read(C.byref(n), C.byref(ms), C.byref(b)))
+    return n.value, ms.value, b.value
 
 
 def _is_torch(x):

@@ -31,7 +31,8 @@ class Options(C.Structure):
         ("mu0", C.c_double), ("mu_factor", C.c_double), ("frac_to_boundary", C.c_double),
         ("final_tol", C.c_double), ("accept_relres", C.c_double),
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
-        ("max_newton", C.c_int32), ("inner_restart", C.c_int32),
+        ("max_newton", C.c_int32), ("inner_restart", C.c_int32), ("max_inner_S", C.c_int32),
+        ("step_rule", C.c_int32),
         ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p),
     ]
@@ -92,6 +93,8 @@ SIGNATURES = {
     "ot_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_outputs": (C.c_int, [C.c_void_p, dptr, dptr, C.c_void_p]),
     "ot_last_error": (C.c_char_p, []),
+    "ot_kprof_select": (C.c_int, [C.c_int32]),
+    "ot_kprof_read": (C.c_int, [C.POINTER(C.c_int64), dptr, dptr]),
     "otbb_debug_structured_sizes": (C.c_int, [C.c_int32, C.c_int32, iptr]),
     "otbb_debug_structured_arrays": (C.c_int, [C.c_int32, C.c_int32, iptr, iptr, dptr, dptr, dptr,
                                                iptr, iptr, dptr, iptr, dptr, dptr, iptr]),

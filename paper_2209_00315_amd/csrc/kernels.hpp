@@ -290,8 +290,10 @@ __global__ void k_convert(const TI *__restrict__ x, TO *__restrict__ y, size_t n
 // y = a x + b y
 template <typename T>
 __global__ void k_axpby(size_t n, double a, const T *__restrict__ x, double b, T *__restrict__ y) {
+    // b == 0 overwrites y without reading it: y may be uninitialised memory,
+    // whose NaN bit patterns would survive a multiplication by zero.
     for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-        y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+        y[i] = (T)(b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * (double)y[i]);
 }
 
 // partial sums of squares
@@ -517,7 +519,7 @@ __global__ void k_tri_factor(int nc, int K, const double *__restrict__ d0, const
 // a chunk of TC levels are issued before the dependent arithmetic so that
 // each thread keeps TC memory requests in flight (one thread per cell gives
 // only nc threads, so latency hiding has to come from within the thread).
-template <typename T>
+template <typename T, int FINE = 0>
 __global__ void k_tri_solve(int nc, int K, const T *__restrict__ inv_dd, const T *__restrict__ lm,
                             const T *__restrict__ up, const T *__restrict__ r, T *__restrict__ x) {
     constexpr int TC = 8;
@@ -651,8 +653,8 @@ __global__ void k_mg_diag(LevelView L, const T *__restrict__ w, T *__restrict__ 
     dinv[(size_t)k * L.n + i] = (T)(d > 0.0 ? 1.0 / d : 0.0);
 }
 
-template <typename T>
-__device__ __forceinline__ double lap_row(const LevelView &L, const T *w, const T *x, int i) {
+template <typename TW, typename TX>
+__device__ __forceinline__ double lap_row(const LevelView &L, const TW *w, const TX *x, int i) {
     const double xi = (double)x[i];
     double v = 0.0;
     for (int t = 0; t < L.w; ++t) {
@@ -663,11 +665,12 @@ __device__ __forceinline__ double lap_row(const LevelView &L, const T *w, const 
     return v;
 }
 
-template <typename T>
-__global__ void k_mg_apply(LevelView L, const T *__restrict__ w, const T *__restrict__ x, T *__restrict__ y) {
+// y = A x on every slice; weights TW (FP32 in the mixed path), vectors TX
+template <typename TW, typename TX>
+__global__ void k_mg_apply(LevelView L, const TW *__restrict__ w, const TX *__restrict__ x, TX *__restrict__ y) {
     const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     if (i >= L.n) return;
-    y[(size_t)k * L.n + i] = (T)lap_row(L, w + (size_t)k * L.ne, x + (size_t)k * L.n, i);
+    y[(size_t)k * L.n + i] = (TX)lap_row(L, w + (size_t)k * L.ne, x + (size_t)k * L.n, i);
 }
 
 // Chebyshev smoothing of D^-1 A on [lo, hi] (Saad, Alg. 12.1):
@@ -688,7 +691,9 @@ __global__ void k_cheb_init(LevelView L, const T *__restrict__ w, const T *__res
 }
 
 // step: x += d; r -= D^-1 A d; d' = c1 d + c2 r
-template <typename T>
+// FINE tags the launches at the finest level, so that profilers list them
+// as a kernel of their own (one launch shape)
+template <typename T, int FINE = 0>
 __global__ void k_cheb_step(LevelView L, const T *__restrict__ w, const T *__restrict__ dinv, T *__restrict__ x,
                             T *__restrict__ r, const T *__restrict__ d, T *__restrict__ dn, double c1, double c2) {
     const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
@@ -887,19 +892,25 @@ __global__ void k_add_shift(int nf, const double *__restrict__ shift, double *__
 }
 
 // ds = (h - s drho)/rho with h = -(rho s - mu); partial min of the step ratios
+// ds = (h - s drho) / rho and the largest steps keeping rho (part[b]) and
+// s (part[nblk + b]) positive, per block
 __global__ void k_ds_ratio(size_t n, StateView S, double mu, const double *__restrict__ drho,
                            double *__restrict__ ds, double *__restrict__ part) {
-    double am = DBL_MAX;
+    double ap = DBL_MAX, ad = DBL_MAX;
     for (size_t q = (size_t)blockIdx.x * BS + threadIdx.x; q < n; q += (size_t)gridDim.x * BS) {
         const double r = S.rho[q], s = S.s[q], dr = drho[q];
         const double h = -(r * s - mu);
         const double d = (h - s * dr) / r;
         ds[q] = d;
-        if (dr < 0) am = fmin(am, -r / dr);
-        if (d < 0) am = fmin(am, -s / d);
+        if (dr < 0) ap = fmin(ap, -r / dr);
+        if (d < 0) ad = fmin(ad, -s / d);
     }
-    am = block_min(am);
-    if (threadIdx.x == 0) part[blockIdx.x] = am;
+    ap = block_min(ap);
+    ad = block_min(ad);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = ap;
+        part[gridDim.x + blockIdx.x] = ad;
+    }
 }
 
 // x += alpha dx

@@ -11,12 +11,55 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kprof.hpp"
 #include "mesh.hpp"
 
 using namespace otbb;
 using namespace otbb::kern;
 
 namespace otbb {
+
+namespace kprof {
+Prof &prof() {
+    static Prof p;
+    return p;
+}
+// synchronise with every pending pair and add its time (caller holds mu)
+void drain(Prof &P) {
+    for (size_t i = 0; i < P.used; ++i) {
+        OT_HIP(hipEventSynchronize(P.pool[i].second));
+        float t = 0.0f;
+        OT_HIP(hipEventElapsedTime(&t, P.pool[i].first, P.pool[i].second));
+        P.ms += t;
+        P.bytes += P.pend[i];
+        P.launches++;
+    }
+    P.used = 0;
+}
+void begin(hipStream_t s) {
+    Prof &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.used == P.pool.size()) {
+        if (P.pool.size() < 4096) {
+            std::pair<hipEvent_t, hipEvent_t> e;
+            OT_HIP(hipEventCreate(&e.first));
+            OT_HIP(hipEventCreate(&e.second));
+            P.pool.push_back(e);
+            P.pend.push_back(0.0);
+        } else {
+            drain(P);
+        }
+    }
+    OT_HIP(hipEventRecord(P.pool[P.used].first, s));
+}
+void end(hipStream_t s, double bytes) {
+    Prof &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    OT_HIP(hipEventRecord(P.pool[P.used].second, s));
+    P.pend[P.used] = bytes;
+    P.used++;
+}
+}  // namespace kprof
 
 // Largest Krylov basis any option combination can request (restart and
 // inner_restart are validated against it); sizes every Krylov scratch.
@@ -179,7 +222,14 @@ static void apply_saddle(ot_state *st, const double *x, double *y) {
     double *cs = st->sums.p;                 // a'^T x_rho^k
     double *us = st->sums.p + K + 2;         // 1^T u^k
     slice_sums<double>(st, x + st->nphi, m->ac, nc, K, cs);
-    k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mv, sv, x, cs, y);
+    {
+        // x, phi, y over the potential block; x_rho and rho once; geometry once
+        const MeshHost &h = m->h;
+        const double bytes = 8.0 * (3.0 * st->nphi + 2.0 * st->mrho) + 8.0 * h.wf * nf + 12.0 * h.wo * nf +
+                             40.0 * h.ne;
+        kprof::Scope ks(OT_KPROF_SADDLE_PHI, st->stream, bytes);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mv, sv, x, cs, y);
+    }
     dim3 gc = grid2(nc, K);
     k_opB<<<gc, BS, 0, st->stream>>>(mv, sv, x, x + st->nphi, cs, 1, y + st->nphi, st->red.part);
     k_seg_final<<<K, BS, 0, st->stream>>>(st->red.part, gc.x, us);
@@ -203,7 +253,10 @@ static double cgs2(ot_state *st, const T *V, size_t ld, int nv, T *w, size_t n, 
     double *h1 = R.dev.p, *h2 = R.dev.p + kMaxBasis, *nr = R.dev.p + 2 * kMaxBasis;
     for (int pass = 0; pass < 2; ++pass) {
         double *hp = pass ? h2 : h1;
-        k_multidot<T><<<dim3(nblk, ng), BS, 0, st->stream>>>(n, V, ld, nv, w, R.part);
+        {
+            kprof::Scope ks(OT_KPROF_MULTIDOT, st->stream, (double)sizeof(T) * (nv + 1.0) * n);
+            k_multidot<T><<<dim3(nblk, ng), BS, 0, st->stream>>>(n, V, ld, nv, w, R.part);
+        }
         k_seg_final<<<nv, BS, 0, st->stream>>>(R.part, nblk, hp);
         k_gs_update<T><<<nblk, BS, 0, st->stream>>>(n, V, ld, nv, hp, w, R.part);
     }
@@ -264,7 +317,11 @@ struct BBPrec : PrecBase {
     DBuf<T> inv_dd, lm, up;
     DBuf<T> cT, dT, rhsS, zS, yT, bT, uT, vT, tmpm, tmpm2, tmpm3, probe;
     DBuf<T> VS, rhsc;                          // inner GMRES basis, scaled rhs
-    DBuf<T> px, pr, pz, pp, pq;                // PCG work
+    // PCG work: the Krylov vectors and the operator are FP64 in both paths;
+    // only the V-cycle (vb -> vx) runs in T.  An all-FP32 PCG stalls above
+    // the 1e-6 relative residual the outer FGMRES needs at small mu.
+    DBuf<double> px, pr, pz, pp, pq;
+    DBuf<T> vb, vx;
     DBuf<double> coef;                         // per-slice alpha / beta
     // pseudo-Schur multigrid: per level >= 1 the Galerkin operator and its
     // time-line factors; per level work vectors (level 0 uses mrho sizes)
@@ -308,6 +365,7 @@ struct BBPrec : PrecBase {
         VS.alloc((size_t)(mS + 1) * mrho);
         rhsc.alloc(mrho);
         px.alloc(nphi); pr.alloc(nphi); pz.alloc(nphi); pp.alloc(nphi); pq.alloc(nphi);
+        vb.alloc(nphi); vx.alloc(nphi);
         coef.alloc(2 * (K + 2));
         nsl = (int)m->slv.size();
         sv.clear(); sinv.clear(); slm.clear(); sup.clear(); sb.clear(); sx.clear(); sr.clear(); stt.clear();
@@ -343,7 +401,7 @@ struct BBPrec : PrecBase {
 
     void s_tri(ot_state *st, int l, const T *r, T *x) {
         const int n = st->mesh->slv[l].n;
-        if (l == 0) k_tri_solve<T><<<grid1(n, 1 << 20), BS, 0, st->stream>>>(n, K, inv_dd, lm, up, r, x);
+        if (l == 0) tri_apply(st, r, x);
         else k_tri_solve<T><<<grid1(n, 1 << 20), BS, 0, st->stream>>>(n, K, sinv[l], slm[l], sup[l], r, x);
     }
 
@@ -464,12 +522,28 @@ struct BBPrec : PrecBase {
         hipStream_t s = st->stream;
         MeshView mv = mesh_view(m);
         k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, z, uT);
-        k_schur_btilde<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, st->dt, z, uT, g, vT);
-        k_schur_out<T><<<grid2(nc, K), BS, 0, s>>>(mv, K, st->dt, z, vT, g, wc, rhoT, sT, out);
+        const double b = sizeof(T), S1 = K + 1;
+        const MeshHost &h = m->h;
+        {
+            // z, u, g, v once; overlap, cell-edge and edge geometry once
+            const double bytes = b * ((double)K * nc + 2.0 * S1 * nf + S1 * ne) +
+                                 12.0 * h.wo * nf + 8.0 * h.wf * nf + 28.0 * ne + 8.0 * nf;
+            kprof::Scope ks(OT_KPROF_SCHUR_BTILDE, s, bytes);
+            k_schur_btilde<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, st->dt, z, uT, g, vT);
+        }
+        {
+            // z, v, g, w~, rho, s, out once; coarse-cell geometry once
+            const double bytes = b * (4.0 * K * nc + S1 * nf + S1 * ne + (double)K * nce) + 8.0 * h.wcc * nc +
+                                 12.0 * h.woc * nc + 12.0 * h.wr * nc + 16.0 * ne;
+            kprof::Scope ks(OT_KPROF_SCHUR_OUT, s, bytes);
+            k_schur_out<T><<<grid2(nc, K), BS, 0, s>>>(mv, K, st->dt, z, vT, g, wc, rhoT, sT, out);
+        }
     }
 
     void tri_apply(ot_state *st, const T *r, T *x) {
-        k_tri_solve<T><<<grid1(nc, 1 << 20), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, r, x);
+        // reads r, l, u, 1/d; writes x (all K x nc)
+        kprof::Scope ks(OT_KPROF_TRI_FINE, st->stream, 5.0 * sizeof(T) * (double)K * nc);
+        k_tri_solve<T, 1><<<grid1(nc, 1 << 20), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, r, x);
     }
 
     // right-preconditioned restarted GMRES on the pseudo-Schur system; w = 0 start
@@ -536,8 +610,17 @@ struct BBPrec : PrecBase {
         T *d = ld[l], *d2 = ld2[l];
         for (int it = 0; it < deg; ++it) {
             const double rho_new = 1.0 / (2.0 * sigma - rho_old);
-            k_cheb_step<T><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
-                                             2.0 * rho_new / delta);
+            if (l == 0) {
+                // x, r read and written; d, 1/D read; d' written; weights and ELL once
+                const double S1 = K + 1;
+                kprof::Scope ks(OT_KPROF_CHEB_FINE, s,
+                                sizeof(T) * (7.0 * S1 * L.n + S1 * L.ne) + 8.0 * L.w * L.n);
+                k_cheb_step<T, 1><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
+                                                    2.0 * rho_new / delta);
+            } else {
+                k_cheb_step<T><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
+                                                 2.0 * rho_new / delta);
+            }
             rho_old = rho_new;
             std::swap(d, d2);
         }
@@ -560,50 +643,58 @@ struct BBPrec : PrecBase {
     }
 
     // PCG on the K+1 slices A^k x^k = b^k (b already zero-mean); x zero-mean on exit
-    int pcg(ot_state *st, const T *b, T *x, double tol, int maxit) {
+    // preconditioner of the PCG: one T-precision V-cycle z = M^-1 r
+    void pcg_prec(ot_state *st, const double *r, double *z) {
+        hipStream_t s = st->stream;
+        k_convert<T, double><<<grid1(nphi), BS, 0, s>>>(r, vb, nphi);
+        vcycle(st, 0, vb, vx);
+        k_convert<double, T><<<grid1(nphi), BS, 0, s>>>(vx, z, nphi);
+    }
+
+    int pcg(ot_state *st, const T *b, double *x, double tol, int maxit) {
         const ot_mesh *m = st->mesh;
         hipStream_t s = st->stream;
         const int S = K + 1;
         LevelView L0 = lview(m, 0);
         dim3 gr = grid2(nf, S);
         double *dsum = st->sums.p;               // scratch (>= S)
-        k_fill<T><<<grid1(nphi), BS, 0, s>>>(x, nphi, (T)0);
-        k_convert<T, T><<<grid1(nphi), BS, 0, s>>>(b, pr.p, nphi);
+        k_fill<double><<<grid1(nphi), BS, 0, s>>>(x, nphi, 0.0);
+        k_convert<double, T><<<grid1(nphi), BS, 0, s>>>(b, pr.p, nphi);
         std::vector<double> bn(S), rz(S), alpha(S), beta(S);
         std::vector<char> active(S, 1);
         {
-            const double *h = st->red.fetch(slice_dots<T>(st, b, b, nf, S, dsum), S);
+            const double *h = st->red.fetch(slice_dots<double>(st, pr.p, pr.p, nf, S, dsum), S);
             for (int k = 0; k < S; ++k) { bn[k] = std::sqrt(h[k]); active[k] = bn[k] > 0.0; }
         }
         if (std::none_of(active.begin(), active.end(), [](char c) { return c; })) return 0;
-        vcycle(st, 0, pr, pz);
+        pcg_prec(st, pr, pz);
         {
-            const double *h = st->red.fetch(slice_dots<T>(st, pr.p, pz.p, nf, S, dsum), S);
+            const double *h = st->red.fetch(slice_dots<double>(st, pr.p, pz.p, nf, S, dsum), S);
             for (int k = 0; k < S; ++k) rz[k] = h[k];
         }
-        k_convert<T, T><<<grid1(nphi), BS, 0, s>>>(pz.p, pp.p, nphi);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(pz.p, pp.p, nphi);
         int it = 0;
         for (it = 1; it <= maxit; ++it) {
-            k_mg_apply<T><<<gr, BS, 0, s>>>(L0, lw[0], pp, pq);
-            const double *h = st->red.fetch(slice_dots<T>(st, pp.p, pq.p, nf, S, dsum), S);
+            k_mg_apply<T, double><<<gr, BS, 0, s>>>(L0, lw[0], pp, pq);
+            const double *h = st->red.fetch(slice_dots<double>(st, pp.p, pq.p, nf, S, dsum), S);
             for (int k = 0; k < S; ++k) alpha[k] = (active[k] && h[k] > 0.0) ? rz[k] / h[k] : 0.0;
             OT_HIP(hipMemcpyAsync(coef.p, alpha.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
-            k_pcg_xr<T><<<gr, BS, 0, s>>>(nf, coef, pp, pq, x, pr);
-            const double *h2 = st->red.fetch(slice_dots<T>(st, pr.p, pr.p, nf, S, dsum), S);
+            k_pcg_xr<double><<<gr, BS, 0, s>>>(nf, coef, pp, pq, x, pr);
+            const double *h2 = st->red.fetch(slice_dots<double>(st, pr.p, pr.p, nf, S, dsum), S);
             bool any = false;
             for (int k = 0; k < S; ++k) {
                 if (active[k] && std::sqrt(std::max(h2[k], 0.0)) <= tol * bn[k]) active[k] = 0;
                 any = any || active[k];
             }
             if (!any) break;
-            vcycle(st, 0, pr, pz);
-            const double *h3 = st->red.fetch(slice_dots<T>(st, pr.p, pz.p, nf, S, dsum), S);
+            pcg_prec(st, pr, pz);
+            const double *h3 = st->red.fetch(slice_dots<double>(st, pr.p, pz.p, nf, S, dsum), S);
             for (int k = 0; k < S; ++k) {
                 beta[k] = (active[k] && rz[k] != 0.0) ? h3[k] / rz[k] : 0.0;
                 if (active[k]) rz[k] = h3[k];
             }
             OT_HIP(hipMemcpyAsync(coef.p + S, beta.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
-            k_pcg_p<T><<<gr, BS, 0, s>>>(nf, coef.p + S, pz, pp);
+            k_pcg_p<double><<<gr, BS, 0, s>>>(nf, coef.p + S, pz, pp);
         }
         OT_HIP(hipStreamSynchronize(s));
         return std::min(it, maxit);
@@ -628,7 +719,7 @@ struct BBPrec : PrecBase {
     int laplace_solve_d(ot_state *st, const double *b, double *x, double tol, int maxit) override {
         k_convert<T, double><<<grid1(nphi), BS, 0, st->stream>>>(b, bT, nphi);
         int its = pcg(st, bT, px, tol, maxit);
-        k_convert<double, T><<<grid1(nphi), BS, 0, st->stream>>>(px, x, nphi);
+        k_convert<double, double><<<grid1(nphi), BS, 0, st->stream>>>(px, x, nphi);
         return its;
     }
     size_t level_data_d(ot_state *st, int level, int what, double *out) override {
@@ -639,9 +730,9 @@ struct BBPrec : PrecBase {
         return n;
     }
     void vcycle_d(ot_state *st, const double *b, double *x) override {
-        k_convert<T, double><<<grid1(nphi), BS, 0, st->stream>>>(b, pr, nphi);
-        vcycle(st, 0, pr, pz);
-        k_convert<double, T><<<grid1(nphi), BS, 0, st->stream>>>(pz, x, nphi);
+        k_convert<T, double><<<grid1(nphi), BS, 0, st->stream>>>(b, vb, nphi);
+        vcycle(st, 0, vb, vx);
+        k_convert<double, T><<<grid1(nphi), BS, 0, st->stream>>>(vx, x, nphi);
     }
 
     // z = P_BB^-1 r (FP64 in/out)
@@ -657,7 +748,7 @@ struct BBPrec : PrecBase {
         slice_sums<T>(st, dT.p, nullptr, nc, K, dsum);
         dim3 gc = grid2(nc, K);
         k_schur_rhs<T><<<gc, BS, 0, s>>>(m->ac, nc, st->area, dsum, rhoT, dT, rhsS);
-        st->acc.inner_S_iters += gmres_schur(st, rhsS, zS, tolS, maxit);
+        st->acc.inner_S_iters += gmres_schur(st, rhsS, zS, tolS, st->opt.max_inner_S);
         // (ii) y = P^T M'^-1 A~ z
         k_coarse_lap_scaled<T><<<gc, BS, 0, s>>>(mesh_view(m), zS, wc, yT);
         double *ys = st->sums.p + 3 * (K + 2);
@@ -671,9 +762,9 @@ struct BBPrec : PrecBase {
         k_slice_shift<T><<<gf, BS, 0, s>>>(nf, bs, 1.0 / nf, bT);
         // (iv) K+1 Laplacian solves, zero-sum solutions
         st->acc.inner_A_iters += pcg(st, bT, px, tolA, maxit);
-        slice_sums<T>(st, px.p, nullptr, nf, K + 1, bs);
-        k_slice_shift<T><<<gf, BS, 0, s>>>(nf, bs, 1.0 / nf, px);
-        k_convert<double, T><<<grid1(nphi), BS, 0, s>>>(px, z, nphi);
+        slice_sums<double>(st, px.p, nullptr, nf, K + 1, bs);
+        k_slice_shift<double><<<gf, BS, 0, s>>>(nf, bs, 1.0 / nf, px);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(px, z, nphi);
         k_convert<double, T><<<grid1(mrho), BS, 0, s>>>(yT, z + nphi, mrho);
         st->acc.prec_applies++;
     }
@@ -702,12 +793,26 @@ static void linearize(ot_state *st) {
 // ---------------------------------------------------------------------------
 // FGMRES on J_P with the BB preconditioner: x = J_P^-1 b (x zero start)
 // ---------------------------------------------------------------------------
+// Grow a column store of length-N vectors to hold at least `cols` columns
+// (capacity doubles, capped at `cap`), keeping the columns already written.
+// Without restart the basis can reach 400 columns; growing on demand keeps
+// the footprint at what the iteration count actually needs.
+static void ensure_cols(ot_state *st, DBuf<double> &B, int cols, int cap) {
+    const size_t N = st->N;
+    if (B.n >= (size_t)cols * N) return;
+    const int have = (int)(B.n / N);
+    const int want = std::max(cols, std::min(cap, std::max(16, 2 * have)));
+    DBuf<double> nb((size_t)want * N);
+    if (B.n) OT_HIP(hipMemcpyAsync(nb.p, B.p, B.n * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
+    OT_HIP(hipStreamSynchronize(st->stream));
+    B = std::move(nb);
+}
+
 static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int maxit, double *res_out) {
     hipStream_t s = st->stream;
     const size_t N = st->N;
-    const int m = std::max(1, st->opt.restart);
-    if (st->V.n < (size_t)(m + 1) * N) st->V.alloc((size_t)(m + 1) * N);
-    if (st->Z.n < (size_t)m * N) st->Z.alloc((size_t)m * N);
+    const int m = std::max(1, std::min(st->opt.restart, maxit));
+    ensure_cols(st, st->V, 1, m + 1);
     k_fill<double><<<grid1(N), BS, 0, s>>>(x, N, 0.0);
     double beta = norm2<double>(st, b, N);
     *res_out = beta;
@@ -722,6 +827,8 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
         G.reset(beta);
         int j = 0;
         for (; j < m && its < maxit; ++j) {
+            ensure_cols(st, st->Z, j + 1, m);
+            ensure_cols(st, st->V, j + 2, m + 1);
             double *zj = st->Z.p + (size_t)j * N;
             st->prec->apply(st, st->V.p + (size_t)j * N, zj);
             double *wn = st->V.p + (size_t)(j + 1) * N;
@@ -843,20 +950,27 @@ static int newton_step(ot_state *st, double *res_before) {
     int nblk = grid1(st->mrho);
     k_ds_ratio<<<nblk, BS, 0, s>>>(st->mrho, sv, st->mu, drho, st->ds, st->red.part);
     k_min_final<<<1, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
-    const double amax = st->red.fetch(st->red.dev, 1)[0];
-    const double alpha = std::min(1.0, st->opt.frac_to_boundary * amax);
-    k_axpy<<<grid1(st->nphi), BS, 0, s>>>(st->nphi, alpha, st->sol, st->phi);
-    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha, drho, st->rho);
-    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha, st->ds, st->s);
+    k_min_final<<<1, BS, 0, s>>>(st->red.part.p + nblk, nblk, st->red.dev.p + 1);
+    const double *am = st->red.fetch(st->red.dev, 2);
+    const double tau = st->opt.frac_to_boundary;
+    const double a_p = std::min(1.0, tau * am[0]), a_d = std::min(1.0, tau * am[1]);
+    // OT_STEP_COMMON: one step for (phi, rho, s); OT_STEP_SPLIT: phi and rho
+    // take the largest step keeping rho positive, s its own
+    const bool split = st->opt.step_rule == OT_STEP_SPLIT;
+    const double alpha = std::min(a_p, a_d);
+    const double alpha_p = split ? a_p : alpha, alpha_d = split ? a_d : alpha;
+    k_axpy<<<grid1(st->nphi), BS, 0, s>>>(st->nphi, alpha_p, st->sol, st->phi);
+    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha_p, drho, st->rho);
+    k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha_d, st->ds, st->s);
     renormalize(st);
     OT_HIP(hipStreamSynchronize(s));
     st->lin_valid = false;
     st->acc.newton_steps++;
     if (st->opt.verbose) {
         const double np = std::max<int64_t>(1, st->acc.prec_applies - p0);
-        fprintf(stderr, "  mu %.3e |F| %.3e fgmres %d relres %.2e inner S %.1f A %.1f alpha %.3f (%.3fs)\n",
+        fprintf(stderr, "  mu %.3e |F| %.3e fgmres %d relres %.2e inner S %.1f A %.1f alpha %.3f (rho %.3f s %.3f) (%.3fs)\n",
                 st->mu, fn, st->last_iters, st->last_relres, (st->acc.inner_S_iters - s0) / np,
-                (st->acc.inner_A_iters - a0) / np, alpha, now_s() - t0);
+                (st->acc.inner_A_iters - a0) / np, alpha, a_p, a_d, now_s() - t0);
     }
     return rc;
 }
@@ -943,7 +1057,8 @@ void check_options(const ot_options &o) {
     OT_REQUIRE(o.mu0 > 0 && o.mu_factor > 0 && o.mu_factor < 1, OT_EINVAL, "bad mu schedule");
     OT_REQUIRE(o.frac_to_boundary > 0 && o.frac_to_boundary < 1, OT_EINVAL, "bad step fraction");
     OT_REQUIRE(o.accept_relres >= 0 && o.accept_relres < 1, OT_EINVAL, "bad accept_relres");
-    OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart < kMaxBasis && o.max_inner >= 1 &&
+    OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart < kMaxBasis && o.max_inner >= 1 && o.max_inner_S >= 1 &&
+                   (o.step_rule == OT_STEP_COMMON || o.step_rule == OT_STEP_SPLIT) &&
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
                OT_EINVAL, "bad iteration caps");
     OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
@@ -1050,14 +1165,39 @@ extern "C" {
 void ot_options_default(ot_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
-    o->tol = 1e-6; o->eps_out = 1e-5; o->eps_in_S = 1e-1; o->eps_in_A = 1e-4;
+    o->tol = 1e-6; o->eps_out = 1e-5; o->eps_in_S = 1e-1; o->eps_in_A = 1e-6;
     o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0;
     o->accept_relres = 1e-2;
-    o->max_fgmres = 400; o->restart = 100; o->max_inner = 200; o->max_newton = 20; o->inner_restart = 30;
+    o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 60; o->inner_restart = 30;
+    o->max_inner_S = 10;
+    o->step_rule = OT_STEP_COMMON;
     o->precision = OT_MIXED; o->mem_kind = OT_HOST; o->verbose = 0; o->stream = nullptr;
 }
 
 const char *ot_last_error(void) { return g_last_error.c_str(); }
+
+int ot_kprof_select(int32_t kernel) {
+    return guard([&] {
+        OT_REQUIRE(kernel >= OT_KPROF_NONE && kernel <= OT_KPROF_SADDLE_PHI, OT_EINVAL, "unknown kernel id");
+        kprof::Prof &P = kprof::prof();
+        std::lock_guard<std::mutex> lk(P.mu);
+        for (size_t i = 0; i < P.used; ++i) OT_HIP(hipEventSynchronize(P.pool[i].second));
+        P.used = 0;
+        P.launches = 0; P.ms = 0.0; P.bytes = 0.0;
+        P.sel = kernel;
+    });
+}
+
+int ot_kprof_read(int64_t *launches, double *ms, double *bytes) {
+    return guard([&] {
+        kprof::Prof &P = kprof::prof();
+        std::lock_guard<std::mutex> lk(P.mu);
+        kprof::drain(P);
+        if (launches) *launches = P.launches;
+        if (ms) *ms = P.ms;
+        if (bytes) *bytes = P.bytes;
+    });
+}
 
 int ot_mesh_create(const ot_mesh_desc *d, ot_mesh **out) {
     return guard([&] {

@@ -106,7 +106,7 @@ def test_schur_prec_exact_inner(case, precision, tol):
     phi, rho, s = r.phi, r.rho, r.s
     inner = 1e-13 if precision == "fp64" else 1e-6
     st = _gpu_state(mg, prob, phi, rho, s, r.mu, precision=precision, eps_in_S=inner, eps_in_A=inner,
-                    max_inner=2000, inner_restart=40)
+                    max_inner=2000, max_inner_S=2000, inner_restart=40)
     r = np.random.default_rng(14).standard_normal(st.N)
     z = st.apply_schur_prec(r)
     K, nf = prob.K, prob.nf
@@ -123,7 +123,7 @@ def test_newton_step_parity(case):
     equals the oracle's direct step."""
     name, prob, mg = case
     st = ot.State(mg, prob.rho_in, prob.rho_f, prob.K, precision="fp64", eps_out=1e-12, eps_in_S=1e-6,
-                  eps_in_A=1e-6, max_fgmres=600, restart=60)
+                  eps_in_A=1e-6, max_fgmres=600, restart=60, max_inner_S=200, tol=1e-14)
     rc, stats, res = st.newton_step()
     phi, rho, s, mu = st.export()
     p0, r0, s0 = initial_point(prob)
@@ -192,7 +192,7 @@ def test_gradient_parity():
     gi_ref, gf_ref = cost_gradient(prob, ref.phi, ref.rho, ref.s)
     mesh = ot.Mesh.structured(n)
     st = ot.State(mesh, ri, rf, K, precision="fp64", eps_out=1e-12, eps_in_S=1e-8, eps_in_A=1e-8,
-                  max_fgmres=600, restart=60)
+                  max_fgmres=600, restart=60, max_inner_S=200)
     st.import_(ref.phi.ravel(), ref.rho.ravel(), ref.s.ravel(), ref.mu)
     gi, gf = st.gradient()
     e1 = np.abs(gi - gi_ref).max() / np.abs(gi_ref).max()

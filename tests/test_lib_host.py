@@ -42,7 +42,7 @@ def test_option_defaults():
     o = ot.options()
     assert (o.tol, o.eps_out, o.eps_in_S) == (1e-6, 1e-5, 1e-1)
     assert (o.mu0, o.mu_factor, o.frac_to_boundary) == (1.0, 0.2, 0.99)
-    assert (o.max_fgmres, o.max_inner, o.max_newton) == (400, 200, 20)
+    assert (o.max_fgmres, o.max_inner, o.max_inner_S, o.max_newton) == (400, 200, 10, 60)
     assert o.precision == ot.OT_MIXED and o.mem_kind == ot.OT_HOST
 
 

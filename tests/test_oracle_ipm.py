@@ -94,6 +94,21 @@ def test_newton_counts(gaussian16):
     assert max(r.newton_per_mu[:-1]) <= 10
 
 
+def test_split_step_rule_reaches_same_solution(gaussian16):
+    """The relaxed system has one solution per mu (strictly convex barrier
+    problem), so the primal / dual split of the positivity line search must
+    end where the common step ends, with the gap identity intact."""
+    prob, r = gaussian16
+    r2 = solve_ipm(prob, tol=1e-6, final_tol=1e-11, step_rule="split")
+    assert r2.converged
+    assert abs(r2.cost - r.cost) < 1e-9 * r.cost
+    assert np.abs(r2.rho - r.rho).max() < 1e-7 * np.abs(r.rho).max()
+    expect = r2.mu * prob.K * prob.dt
+    assert abs(r2.gap - expect) < 1e-9 * expect
+    with pytest.raises(ValueError):
+        solve_ipm(prob, tol=1e-6, step_rule="bogus")
+
+
 def test_uniform_marginals_closed_form():
     """rho_in = rho_f = 1: rho = 1, s = mu, phi^k = -(k-1) dt mu + c, KE = 0."""
     for mk in (structured_mesh, cartesian_mesh):
