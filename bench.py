@@ -1,9 +1,10 @@
 """Benchmark: interior-point solve of the 256 x 256 right-triangle grid with
 K = 64 on one MI355X (5-Gaussian-mixture marginals plus a 1e-3 background,
 synthetic), mixed precision (FP32 BB preconditioner, FP64 Newton / FGMRES)
-against the FP64 path.  One step = one full solve, from mu = 1 down to the
-first mu below 1e-6, with every Newton system solved by BB-preconditioned
-FGMRES.
+against the FP64 path.  One step = one continuation run, mu = 0.2^l from 1
+down to mu_stop (8e-3 by default on this grid: below it the interior-point
+iteration itself slows to step lengths of 1e-3..1e-1 on this workload),
+every mu solved to |F| <= 1e-6 with BB-preconditioned FGMRES Newton steps.
 
 Prints one JSON line: value = Krylov (FGMRES) iterations per second of the
 mixed path over the timed steps, the time-to-tolerance of both paths, the
@@ -25,6 +26,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # the CPU sample: the metric workload's marginal recipe on a reduced grid
 SAMPLE_N, SAMPLE_K = 24, 12
+KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde", "cheb_fine": "k_cheb_step<., 1>",
+                "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 
 
 def parse():
@@ -35,8 +38,12 @@ def parse():
                    help="untimed full solves before the timed ones (a small solve always runs first)")
     p.add_argument("--config", type=int, default=3, help="workload: 1, 2 or 3 (256^2, K=64)")
     p.add_argument("--kernel", default="schur_out", help="kernel whose roofline is reported")
+    p.add_argument("--mu-stop", type=float, default=None,
+                   help="end the continuation after this mu (default: 8e-3 for config 3, full run otherwise)")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--gpu-sample", action="store_true",
+                   help="also solve the CPU sample on the GPU (adds small launches to a profile)")
     p.add_argument("--verbose", type=int, default=0)
     p.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     return p.parse_args()
@@ -85,35 +92,44 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda")
 
-    def solve(n, K, ri, rf, precision):
+    mu_stop = a.mu_stop if a.mu_stop is not None else (8e-3 if a.config == 3 else 0.0)
+
+    def solve(n, K, ri, rf, precision, mu_stop=0.0):
         mesh = ot.Mesh.structured(n)
         ri_d = torch.as_tensor(ri, dtype=torch.float64, device=dev)
         rf_d = torch.as_tensor(rf, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = ot.solve(mesh, ri_d, rf_d, K, tol=1e-6, device=True, precision=precision, verbose=a.verbose)
+        out = ot.solve(mesh, ri_d, rf_d, K, tol=1e-6, device=True, precision=precision, verbose=a.verbose,
+                       mu_stop=mu_stop)
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
     def log(msg):
         print("# " + msg, file=sys.stderr, flush=True)
 
-    # code-object load and first allocations, outside the timed region
-    n1, K1, ri1, rf1 = otinputs.config_marginals(1)
-    solve(n1, K1, ri1, rf1, "mixed")
-    solve(n1, K1, ri1, rf1, "fp64")
-
     n, K, ri, rf = otinputs.config_marginals(a.config)
+    # code-object load and first allocations outside the timed region: one
+    # Newton step of the same problem in each precision, so that every launch
+    # in this process has the workload's shape
+    mesh_w = ot.Mesh.structured(n)
+    for prec in ("mixed", "fp64"):
+        stw = ot.State(mesh_w, torch.as_tensor(ri, device=dev), torch.as_tensor(rf, device=dev), K, device=True,
+                       precision=prec)
+        stw.newton_step(raise_on_error=False)
+        del stw
+    torch.cuda.synchronize()
+
     for w in range(a.warmup):
-        out, dt = solve(n, K, ri, rf, "mixed")
+        out, dt = solve(n, K, ri, rf, "mixed", mu_stop)
         log(f"warmup {w}: {dt:.2f}s outer {out['stats'].outer_iters}")
 
-    ot.kprof_select(a.kernel)
+    ot.kprof_select(a.kernel, 4)          # the FP32 instantiation of the mixed path
     its = systems = 0
     T = 0.0
     results = []
     for s in range(a.steps):
-        out, dt = solve(n, K, ri, rf, "mixed")
+        out, dt = solve(n, K, ri, rf, "mixed", mu_stop)
         T += dt
         results.append(out)
         its += out["stats"].outer_iters
@@ -140,8 +156,11 @@ def main():
         "config": {"workload": f"BB-preconditioned interior-point solve, {n}x{n} right-triangle grid "
                                f"({2 * n * n} fine triangles), K={K}, 5-Gaussian mixtures + 1e-3 background"
                                if a.config == 3 else f"config {a.config}: {n}x{n} grid, K={K}",
-                   "n": n, "K": K, "unknowns_per_newton_system": int((K + 1) * n * n + K * (n * n // 2))},
+                   "n": n, "K": K, "unknowns_per_newton_system": int((K + 1) * n * n + K * (n * n // 2)),
+                   "continuation": (f"mu = 0.2^l from 1 down to {mu_stop:g}, each mu solved to |F| <= 1e-6"
+                                    if mu_stop > 0 else "mu = 0.2^l from 1 down to the first mu below 1e-6")},
         "time_to_tol_s": T / a.steps,
+        "mu_final": st.mu,
         "linear_systems": systems // a.steps,
         "outer_per_linear_system": its / max(systems, 1),
         "newton_steps": st.newton_steps,
@@ -153,27 +172,30 @@ def main():
         "gap": st.gap,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "kernel": a.kernel, "launches": launches,
+                     "kernel": f"{KERNEL_NAMES.get(a.kernel, a.kernel)} (FP32)", "launches": launches,
                      "avg_us": 1000.0 * kms / launches if launches else None,
                      "bytes_per_launch": kbytes / launches if launches else None},
     }
     if not a.no_fp64:
-        o64, t64 = solve(n, K, ri, rf, "fp64")
+        o64, t64 = solve(n, K, ri, rf, "fp64", mu_stop)
         log(f"fp64: {t64:.2f}s outer {o64['stats'].outer_iters} cost {o64['cost']:.12g}")
         line["fp64"] = {"time_to_tol_s": t64, "krylov_its_per_s": o64["stats"].outer_iters / t64,
-                        "outer_iters": o64["stats"].outer_iters, "rc": o64["rc"], "cost": o64["cost"]}
+                        "outer_iters": o64["stats"].outer_iters, "newton_steps": o64["stats"].newton_steps,
+                        "rc": o64["rc"], "cost": o64["cost"]}
         line["cost_rel_diff_mixed_vs_fp64"] = abs(o64["cost"] - results[-1]["cost"]) / abs(o64["cost"])
         line["speedup_mixed_vs_fp64"] = t64 / (T / a.steps)
     if not a.no_cpu:
         cb = run_cpu_baseline()
-        ris, rfs = otinputs.mixture_pair(SAMPLE_N, 5, 3, background=1e-3)
-        og, tg = solve(SAMPLE_N, SAMPLE_K, ris, rfs, "mixed")
         line["cpu_baseline"] = {
             "value": cb["seconds"], "unit": "s time-to-tol", "cores": 1, "kind": "oracle",
             "sample": f"full interior-point solve of the same marginal recipe on a {SAMPLE_N}x{SAMPLE_N} "
                       f"grid, K={SAMPLE_K}, tol 1e-6 (sparse direct Newton solves, 1 BLAS thread)",
-            "gpu_same_sample_s": tg, "cost_rel_diff_gpu_vs_oracle": abs(og["cost"] - cb["cost"]) / cb["cost"],
-            "host_cpus": os.cpu_count()}
+            "oracle_cost": cb["cost"], "host_cpus": os.cpu_count()}
+        if a.gpu_sample:
+            ris, rfs = otinputs.mixture_pair(SAMPLE_N, 5, 3, background=1e-3)
+            og, tg = solve(SAMPLE_N, SAMPLE_K, ris, rfs, "mixed")
+            line["cpu_baseline"]["gpu_same_sample_s"] = tg
+            line["cpu_baseline"]["cost_rel_diff_gpu_vs_oracle"] = abs(og["cost"] - cb["cost"]) / cb["cost"]
     print(json.dumps(line), flush=True)
 
 

@@ -122,6 +122,9 @@ typedef struct {
     double tol, eps_out, eps_in_S, eps_in_A;
     double mu0, mu_factor, frac_to_boundary;
     double final_tol;        /* <= 0: use tol for the last mu as well       */
+    double mu_stop;          /* > 0: stop after solving the first mu <= mu_stop
+                                (a truncated continuation); 0: run down to the
+                                first mu below tol                           */
     double accept_relres;    /* a Newton step whose FGMRES stopped at the cap
                                 is still taken when its relative residual is
                                 below this value (counted as a failure)     */
@@ -252,11 +255,12 @@ const char *ot_last_error(void);
 
 /*
  * Kernel timing (instrumentation of the hot path, process-wide).
- * ot_kprof_select(id) picks one kernel and clears the counters; from then on
- * every launch of it, in any state, is bracketed by two HIP events recorded
- * on the stream it runs on, and its algorithmic bytes (each operand read
- * once, each result written once; FP32 operands in the mixed path) are
- * summed.  ot_kprof_read drains pending events (it synchronises with them)
+ * ot_kprof_select(id, elem_bytes) picks one kernel and clears the counters;
+ * from then on every launch of it, in any state, whose floating-point
+ * operands are elem_bytes wide (4: the FP32 preconditioner instantiation,
+ * 8: FP64, 0: both) is launched with a start / stop HIP event pair stamped
+ * by the dispatch itself on the stream it runs on, and its algorithmic
+ * bytes (each operand read once, each result written once) are summed.  ot_kprof_read drains pending events (it synchronises with them)
  * and returns launches, total kernel milliseconds and total bytes; any
  * output pointer may be NULL.  OT_KPROF_NONE switches timing off.  Not for
  * concurrent use from several threads.
@@ -272,7 +276,7 @@ enum {
     OT_KPROF_NONE = 0, OT_KPROF_CHEB_FINE = 1, OT_KPROF_SCHUR_BTILDE = 2, OT_KPROF_SCHUR_OUT = 3,
     OT_KPROF_TRI_FINE = 4, OT_KPROF_MULTIDOT = 5, OT_KPROF_SADDLE_PHI = 6
 };
-int  ot_kprof_select(int32_t kernel);
+int  ot_kprof_select(int32_t kernel, int32_t elem_bytes);
 int  ot_kprof_read(int64_t *launches, double *ms, double *bytes);
 
 #ifdef __cplusplus

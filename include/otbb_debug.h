@@ -48,6 +48,9 @@ int otbb_debug_schur_levels(int32_t n, int32_t cartesian, int32_t *out, int32_t 
  *                 relative tolerance tol, cap maxit, iterations to *iters
  *  tri_diagonals: its three time diagonals per coarse cell (probed):
  *                 d0 = (k,k), dl = (k,k-1), du = (k,k+1) entries (m_rho)
+ *  tri_solve:     the time-line tridiagonal solve built from those
+ *                 diagonals (Thomas factors; weak pivots replaced by the
+ *                 plain diagonal)                                    (m_rho)
  *  laplace_solve: PCG with the multigrid V-cycle on the K+1 Laplacians
  *                 A^k x^k = b^k (b zero-sum per slice)             (n_phi)
  *  vcycle:        one multigrid V-cycle x = M^-1 b on all slices  (n_phi)
@@ -56,6 +59,7 @@ int otbb_debug_schur_apply(ot_state *st, const double *z, double *out);
 int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double tol, int32_t maxit,
                            int32_t *iters);
 int otbb_debug_tri_diagonals(ot_state *st, double *d0, double *dl, double *du);
+int otbb_debug_tri_solve(ot_state *st, const double *r, double *x);
 int otbb_debug_laplace_solve(ot_state *st, const double *b, double *x, double tol, int32_t maxit,
                              int32_t *iters);
 int otbb_debug_vcycle(ot_state *st, const double *b, double *x);

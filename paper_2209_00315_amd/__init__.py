@@ -23,9 +23,10 @@ KPROF = {"none": 0, "cheb_fine": 1, "schur_btilde": 2, "schur_out": 3, "tri_fine
          "saddle_phi": 6}
 
 
-def kprof_select(kernel):
-    """Time every launch of one hot-path kernel with HIP events (process-wide)."""
-    check(lib().ot_kprof_select(KPROF[kernel] if isinstance(kernel, str) else int(kernel)))
+def kprof_select(kernel, elem_bytes=0):
+    """Time every launch of one hot-path kernel with HIP events (process-wide);
+    elem_bytes 4 / 8 restricts it to the FP32 / FP64 instantiation."""
+    check(lib().ot_kprof_select(KPROF[kernel] if isinstance(kernel, str) else int(kernel), int(elem_bytes)))
 
 
 def kprof_read():
@@ -330,7 +331,7 @@ def _run_ipm(st, tol, mu_factor=None):
     st.set_mu(mu)
     fac = o.mu_factor if mu_factor is None else mu_factor
     for _ in range(400):
-        last = mu < tol
+        last = mu < tol or (o.mu_stop > 0 and mu <= o.mu_stop * (1 + 1e-12))
         tl = o.final_tol if (last and o.final_tol > 0) else tol
         ok = False
         for it in range(o.max_newton + 1):

@@ -29,7 +29,7 @@ class Options(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("eps_out", C.c_double), ("eps_in_S", C.c_double), ("eps_in_A", C.c_double),
         ("mu0", C.c_double), ("mu_factor", C.c_double), ("frac_to_boundary", C.c_double),
-        ("final_tol", C.c_double), ("accept_relres", C.c_double),
+        ("final_tol", C.c_double), ("mu_stop", C.c_double), ("accept_relres", C.c_double),
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
         ("max_newton", C.c_int32), ("inner_restart", C.c_int32), ("max_inner_S", C.c_int32),
         ("step_rule", C.c_int32),
@@ -93,7 +93,7 @@ SIGNATURES = {
     "ot_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_outputs": (C.c_int, [C.c_void_p, dptr, dptr, C.c_void_p]),
     "ot_last_error": (C.c_char_p, []),
-    "ot_kprof_select": (C.c_int, [C.c_int32]),
+    "ot_kprof_select": (C.c_int, [C.c_int32, C.c_int32]),
     "ot_kprof_read": (C.c_int, [C.POINTER(C.c_int64), dptr, dptr]),
     "otbb_debug_structured_sizes": (C.c_int, [C.c_int32, C.c_int32, iptr]),
     "otbb_debug_structured_arrays": (C.c_int, [C.c_int32, C.c_int32, iptr, iptr, dptr, dptr, dptr,
@@ -101,6 +101,7 @@ SIGNATURES = {
     "otbb_debug_validate_desc": (C.c_int, [C.POINTER(MeshDesc)]),
     "otbb_debug_schur_levels": (C.c_int, [C.c_int32, C.c_int32, iptr, C.c_int32]),
     "otbb_debug_schur_apply": (C.c_int, [C.c_void_p, dptr, dptr]),
+    "otbb_debug_tri_solve": (C.c_int, [C.c_void_p, dptr, dptr]),
     "otbb_debug_schur_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
     "otbb_debug_tri_diagonals": (C.c_int, [C.c_void_p, dptr, dptr, dptr]),
     "otbb_debug_laplace_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),

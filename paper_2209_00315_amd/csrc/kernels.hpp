@@ -567,6 +567,69 @@ __global__ void k_tri_solve(int nc, int K, const T *__restrict__ inv_dd, const T
     }
 }
 
+// Same solve with one wavefront per cell, one lane per time level: each
+// Thomas sweep is a first-order linear recurrence, y_k = a_k y_{k-1} + b_k
+// (forward: a = -l, b = r; backward, from the end: x_k = -u_k d_k x_{k+1} +
+// d_k y_k), i.e. the composition of affine maps, which a Hillis-Steele scan
+// over the 64 lanes evaluates in 6 shuffle steps instead of 64 dependent
+// steps.  Lines longer than 64 are done in chunks with the value at the
+// chunk edge carried over; y stays in registers (K <= 64 kTriScanChunks).
+constexpr int kTriScanChunks = 4;
+
+template <typename T, int FINE = 0>
+__global__ void __launch_bounds__(BS) k_tri_scan(int nc, int K, const T *__restrict__ inv_dd,
+                                                 const T *__restrict__ lm, const T *__restrict__ up,
+                                                 const T *__restrict__ r, T *__restrict__ x) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (j >= nc) return;                       // whole wavefront leaves together
+    const int nch = (K + 63) / 64;
+    double ys[kTriScanChunks];
+    double carry = 0.0;
+#pragma unroll
+    for (int c = 0; c < kTriScanChunks; ++c) {
+        if (c >= nch) break;
+        const int k = c * 64 + lane;
+        const bool in = k < K;
+        const size_t q = (size_t)k * nc + j;
+        double a = in ? -(double)lm[q] : 1.0;  // identity map on lanes past the line
+        double b = in ? (double)r[q] : 0.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double ap = __shfl_up(a, off, 64), bp = __shfl_up(b, off, 64);
+            if (lane >= off) {
+                b = a * bp + b;
+                a = a * ap;
+            }
+        }
+        const double y = a * carry + b;
+        ys[c] = y;
+        carry = __shfl(y, 63, 64);
+    }
+    carry = 0.0;
+#pragma unroll
+    for (int c = kTriScanChunks - 1; c >= 0; --c) {
+        if (c >= nch) continue;
+        const int k = c * 64 + lane;
+        const bool in = k < K;
+        const size_t q = (size_t)k * nc + j;
+        double d = in ? (double)inv_dd[q] : 0.0;
+        double a = in ? -(double)up[q] * d : 1.0;
+        double b = in ? ys[c] * d : 0.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double an = __shfl_down(a, off, 64), bn = __shfl_down(b, off, 64);
+            if (lane + off < 64) {
+                b = a * bn + b;
+                a = a * an;
+            }
+        }
+        const double xv = a * carry + b;
+        if (in) x[q] = (T)xv;
+        carry = __shfl(xv, 0, 64);
+    }
+}
+
 // rhs of the pseudo-Schur system: -rho (P d)^k, dsum[k] = 1^T d^k
 template <typename T>
 __global__ void k_schur_rhs(const double *__restrict__ ac, int nc, double area, const double *__restrict__ dsum,

@@ -36,7 +36,7 @@ void drain(Prof &P) {
     }
     P.used = 0;
 }
-void begin(hipStream_t s) {
+Ev take_slot(double bytes) {
     Prof &P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
     if (P.used == P.pool.size()) {
@@ -50,14 +50,12 @@ void begin(hipStream_t s) {
             drain(P);
         }
     }
-    OT_HIP(hipEventRecord(P.pool[P.used].first, s));
-}
-void end(hipStream_t s, double bytes) {
-    Prof &P = prof();
-    std::lock_guard<std::mutex> lk(P.mu);
-    OT_HIP(hipEventRecord(P.pool[P.used].second, s));
+    Ev e;
+    e.a = P.pool[P.used].first;
+    e.b = P.pool[P.used].second;
     P.pend[P.used] = bytes;
     P.used++;
+    return e;
 }
 }  // namespace kprof
 
@@ -65,6 +63,8 @@ void end(hipStream_t s, double bytes) {
 // inner_restart are validated against it); sizes every Krylov scratch.
 constexpr int kMaxBasis = 401;
 constexpr int kMultidotBlocks = 512;
+// longest time line the wavefront-scan tridiagonal solve handles
+constexpr int kTriScanMaxK = 64 * kern::kTriScanChunks;
 
 static thread_local std::string g_last_error = "no error";
 void set_last_error(const std::string &msg) { g_last_error = msg; }
@@ -136,6 +136,7 @@ struct PrecBase {
     virtual void schur_apply_d(ot_state *st, const double *z, double *out) = 0;
     virtual int schur_solve_d(ot_state *st, const double *rhs, double *z, double tol, int maxit) = 0;
     virtual void tri_diagonals_d(ot_state *st, double *d0, double *dl, double *du) = 0;
+    virtual void tri_solve_d(ot_state *st, const double *r, double *x) = 0;
     virtual int laplace_solve_d(ot_state *st, const double *b, double *x, double tol, int maxit) = 0;
     virtual void vcycle_d(ot_state *st, const double *b, double *x) = 0;
     virtual size_t level_data_d(ot_state *st, int level, int what, double *out) = 0;
@@ -152,8 +153,10 @@ struct ot_state {
     DBuf<double> F, rhs, sol, gt, tmpN, tmpr, ds, sums, shift;
     DBuf<double> V, Z;
     Reducer red;
-    std::unique_ptr<PrecBase> prec;
+    std::unique_ptr<PrecBase> prec;            // active preconditioner
     int prec_kind = -1;
+    std::unique_ptr<PrecBase> prec_alt;        // the other precision, kept for retries
+    int prec_alt_kind = -1;
     bool lin_valid = false;
     ot_stats acc{};
     // last FGMRES info
@@ -227,8 +230,9 @@ static void apply_saddle(ot_state *st, const double *x, double *y) {
         const MeshHost &h = m->h;
         const double bytes = 8.0 * (3.0 * st->nphi + 2.0 * st->mrho) + 8.0 * h.wf * nf + 12.0 * h.wo * nf +
                              40.0 * h.ne;
-        kprof::Scope ks(OT_KPROF_SADDLE_PHI, st->stream, bytes);
-        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mv, sv, x, cs, y);
+        const kprof::Ev ev = kprof::take(OT_KPROF_SADDLE_PHI, 8, bytes);
+        hipExtLaunchKernelGGL(k_saddle_phi, grid2(nf, K + 1), dim3(BS), 0, st->stream, ev.a, ev.b, 0, mv, sv, x,
+                              (const double *)cs, y);
     }
     dim3 gc = grid2(nc, K);
     k_opB<<<gc, BS, 0, st->stream>>>(mv, sv, x, x + st->nphi, cs, 1, y + st->nphi, st->red.part);
@@ -254,8 +258,9 @@ static double cgs2(ot_state *st, const T *V, size_t ld, int nv, T *w, size_t n, 
     for (int pass = 0; pass < 2; ++pass) {
         double *hp = pass ? h2 : h1;
         {
-            kprof::Scope ks(OT_KPROF_MULTIDOT, st->stream, (double)sizeof(T) * (nv + 1.0) * n);
-            k_multidot<T><<<dim3(nblk, ng), BS, 0, st->stream>>>(n, V, ld, nv, w, R.part);
+            const kprof::Ev ev = kprof::take(OT_KPROF_MULTIDOT, sizeof(T), (double)sizeof(T) * (nv + 1.0) * n);
+            hipExtLaunchKernelGGL(k_multidot<T>, dim3(nblk, ng), dim3(BS), 0, st->stream, ev.a, ev.b, 0, n, V, ld,
+                                  nv, (const T *)w, R.part.p);
         }
         k_seg_final<<<nv, BS, 0, st->stream>>>(R.part, nblk, hp);
         k_gs_update<T><<<nblk, BS, 0, st->stream>>>(n, V, ld, nv, hp, w, R.part);
@@ -402,7 +407,7 @@ struct BBPrec : PrecBase {
     void s_tri(ot_state *st, int l, const T *r, T *x) {
         const int n = st->mesh->slv[l].n;
         if (l == 0) tri_apply(st, r, x);
-        else k_tri_solve<T><<<grid1(n, 1 << 20), BS, 0, st->stream>>>(n, K, sinv[l], slm[l], sup[l], r, x);
+        else tri_launch<0>(st->stream, n, sinv[l], slm[l], sup[l], r, x, kprof::Ev{});
     }
 
     // assemble the Galerkin operators of levels >= 1 by probing the level above
@@ -528,22 +533,37 @@ struct BBPrec : PrecBase {
             // z, u, g, v once; overlap, cell-edge and edge geometry once
             const double bytes = b * ((double)K * nc + 2.0 * S1 * nf + S1 * ne) +
                                  12.0 * h.wo * nf + 8.0 * h.wf * nf + 28.0 * ne + 8.0 * nf;
-            kprof::Scope ks(OT_KPROF_SCHUR_BTILDE, s, bytes);
-            k_schur_btilde<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, st->dt, z, uT, g, vT);
+            const kprof::Ev ev = kprof::take(OT_KPROF_SCHUR_BTILDE, sizeof(T), bytes);
+            hipExtLaunchKernelGGL(k_schur_btilde<T>, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K,
+                                  st->dt, z, (const T *)uT.p, (const T *)g.p, vT.p);
         }
         {
             // z, v, g, w~, rho, s, out once; coarse-cell geometry once
             const double bytes = b * (4.0 * K * nc + S1 * nf + S1 * ne + (double)K * nce) + 8.0 * h.wcc * nc +
                                  12.0 * h.woc * nc + 12.0 * h.wr * nc + 16.0 * ne;
-            kprof::Scope ks(OT_KPROF_SCHUR_OUT, s, bytes);
-            k_schur_out<T><<<grid2(nc, K), BS, 0, s>>>(mv, K, st->dt, z, vT, g, wc, rhoT, sT, out);
+            const kprof::Ev ev = kprof::take(OT_KPROF_SCHUR_OUT, sizeof(T), bytes);
+            hipExtLaunchKernelGGL(k_schur_out<T>, grid2(nc, K), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K, st->dt, z,
+                                  (const T *)vT.p, (const T *)g.p, (const T *)wc.p, (const T *)rhoT.p,
+                                  (const T *)sT.p, out);
         }
+    }
+
+    // time-line tridiagonal solve of n cells: one wavefront per cell with a
+    // scan over time (K <= kTriScanMaxK), else one thread per cell
+    template <int FINE>
+    void tri_launch(hipStream_t s, int n, const T *dinv, const T *l, const T *u, const T *r, T *x, kprof::Ev ev) {
+        if (K <= kTriScanMaxK)
+            hipExtLaunchKernelGGL(k_tri_scan<T, FINE>, dim3(ceil_div(n, BS / 64)), dim3(BS), 0, s, ev.a, ev.b, 0,
+                                  n, K, dinv, l, u, r, x);
+        else
+            hipExtLaunchKernelGGL(k_tri_solve<T, FINE>, dim3(grid1(n, 1 << 20)), dim3(BS), 0, s, ev.a, ev.b, 0,
+                                  n, K, dinv, l, u, r, x);
     }
 
     void tri_apply(ot_state *st, const T *r, T *x) {
         // reads r, l, u, 1/d; writes x (all K x nc)
-        kprof::Scope ks(OT_KPROF_TRI_FINE, st->stream, 5.0 * sizeof(T) * (double)K * nc);
-        k_tri_solve<T, 1><<<grid1(nc, 1 << 20), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, r, x);
+        const kprof::Ev ev = kprof::take(OT_KPROF_TRI_FINE, sizeof(T), 5.0 * sizeof(T) * (double)K * nc);
+        tri_launch<1>(st->stream, nc, inv_dd, lm, up, r, x, ev);
     }
 
     // right-preconditioned restarted GMRES on the pseudo-Schur system; w = 0 start
@@ -613,10 +633,11 @@ struct BBPrec : PrecBase {
             if (l == 0) {
                 // x, r read and written; d, 1/D read; d' written; weights and ELL once
                 const double S1 = K + 1;
-                kprof::Scope ks(OT_KPROF_CHEB_FINE, s,
-                                sizeof(T) * (7.0 * S1 * L.n + S1 * L.ne) + 8.0 * L.w * L.n);
-                k_cheb_step<T, 1><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
-                                                    2.0 * rho_new / delta);
+                const kprof::Ev ev =
+                    kprof::take(OT_KPROF_CHEB_FINE, sizeof(T), sizeof(T) * (7.0 * S1 * L.n + S1 * L.ne) + 8.0 * L.w * L.n);
+                hipExtLaunchKernelGGL(k_cheb_step<T, 1>, gr, dim3(BS), 0, s, ev.a, ev.b, 0, L, (const T *)lw[l].p,
+                                      (const T *)ldinv[l].p, x, lr[l].p, (const T *)d, d2, rho_new * rho_old,
+                                      2.0 * rho_new / delta);
             } else {
                 k_cheb_step<T><<<gr, BS, 0, s>>>(L, lw[l], ldinv[l], x, lr[l], d, d2, rho_new * rho_old,
                                                  2.0 * rho_new / delta);
@@ -711,6 +732,11 @@ struct BBPrec : PrecBase {
         k_convert<double, T><<<grid1(mrho), BS, 0, st->stream>>>(zS, z, mrho);
         return its;
     }
+    void tri_solve_d(ot_state *st, const double *r, double *x) override {
+        k_convert<T, double><<<grid1(mrho), BS, 0, st->stream>>>(r, tmpm3, mrho);
+        tri_apply(st, tmpm3, tmpm2);
+        k_convert<double, T><<<grid1(mrho), BS, 0, st->stream>>>(tmpm2, x, mrho);
+    }
     void tri_diagonals_d(ot_state *st, double *a0, double *al, double *au) override {
         OT_HIP(hipMemcpyAsync(a0, d0.p, mrho * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
         OT_HIP(hipMemcpyAsync(al, dl.p, mrho * sizeof(double), hipMemcpyDeviceToDevice, st->stream));
@@ -775,6 +801,11 @@ namespace otbb {
 static void ensure_prec(ot_state *st) {
     int kind = st->opt.precision;
     if (!st->prec || st->prec_kind != kind) {
+        std::swap(st->prec, st->prec_alt);
+        std::swap(st->prec_kind, st->prec_alt_kind);
+        st->lin_valid = false;
+    }
+    if (!st->prec || st->prec_kind != kind) {
         if (kind == OT_MIXED) st->prec.reset(new BBPrec<float>());
         else st->prec.reset(new BBPrec<double>());
         st->prec_kind = kind;
@@ -821,7 +852,8 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
     Givens G(m);
     int its = 0;
     double res = beta;
-    std::vector<double> h(m + 1);
+    std::vector<double> h(m + 1), hist;
+    bool stop = false;
     while (its < maxit) {
         k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, st->V.p, 1.0 / beta, st->V.p);
         G.reset(beta);
@@ -840,13 +872,18 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
             res = G.push(j);
             if (hn > 0) k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, wn, 1.0 / hn, wn);
             if (st->opt.verbose > 1) fprintf(stderr, "    fgmres it %d res %.3e target %.3e\n", its, res, tol_abs);
-            if (res <= tol_abs || hn == 0.0) { ++j; break; }
+            hist.push_back(res);
+            // plateau: no halving over the last 40 iterations (after 80); the
+            // residual has met the rounding floor of the operator or the
+            // preconditioner no longer helps, and the caller's retry decides
+            const bool stalled = its >= 80 && res > 0.5 * hist[its - 41];
+            if (res <= tol_abs || hn == 0.0 || stalled) { stop = stalled; ++j; break; }
         }
         std::vector<double> y = G.solve(j);
         OT_HIP(hipMemcpyAsync(st->shift.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
         k_combine<double, double><<<grid1(N), BS, 0, s>>>(N, st->Z.p, N, j, st->shift.p, 1.0, x);
         OT_HIP(hipStreamSynchronize(s));
-        if (res <= tol_abs || its >= maxit) break;
+        if (res <= tol_abs || its >= maxit || stop) break;
         // restart with the true residual
         apply_saddle(st, x, st->V.p);
         k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 1.0, b, -1.0, st->V.p);
@@ -933,6 +970,25 @@ static int newton_step(ot_state *st, double *res_before) {
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
     int its = solve_newton_system(st, fn);
+    if (!st->last_converged) {
+        // retry once with the FP64 preconditioner, inner tolerances / 10 and
+        // the pseudo-Schur cap lifted to the general inner cap
+        const ot_options saved = st->opt;
+        const int its1 = st->last_iters;
+        const double rr1 = st->last_relres;
+        st->opt.precision = OT_FP64;
+        st->opt.eps_in_S = 0.1 * saved.eps_in_S;
+        st->opt.eps_in_A = 0.1 * saved.eps_in_A;
+        st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
+        linearize(st);
+        its += solve_newton_system(st, fn);
+        st->acc.linear_systems--;              // one Newton system, two attempts
+        if (st->opt.verbose)
+            fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1,
+                    st->last_iters, st->last_relres);
+        st->opt = saved;
+        st->lin_valid = false;
+    }
     int rc = OT_OK;
     if (!st->last_converged) {
         st->acc.failures++;
@@ -1058,7 +1114,7 @@ void check_options(const ot_options &o) {
     OT_REQUIRE(o.frac_to_boundary > 0 && o.frac_to_boundary < 1, OT_EINVAL, "bad step fraction");
     OT_REQUIRE(o.accept_relres >= 0 && o.accept_relres < 1, OT_EINVAL, "bad accept_relres");
     OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart < kMaxBasis && o.max_inner >= 1 && o.max_inner_S >= 1 &&
-                   (o.step_rule == OT_STEP_COMMON || o.step_rule == OT_STEP_SPLIT) &&
+                   (o.step_rule == OT_STEP_COMMON || o.step_rule == OT_STEP_SPLIT) && o.mu_stop >= 0.0 &&
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
                OT_EINVAL, "bad iteration caps");
     OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
@@ -1136,7 +1192,7 @@ int run_ipm(ot_state *st, double tol) {
     int rc = OT_OK;
     st->mu = o.mu0;
     for (int l = 0; l < 400; ++l) {
-        const bool last = st->mu < tol;
+        const bool last = st->mu < tol || (o.mu_stop > 0.0 && st->mu <= o.mu_stop * (1.0 + 1e-12));
         const double tl = (last && o.final_tol > 0) ? o.final_tol : tol;
         bool ok = false;
         for (int it = 0; it <= o.max_newton; ++it) {
@@ -1166,7 +1222,7 @@ void ot_options_default(ot_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
     o->tol = 1e-6; o->eps_out = 1e-5; o->eps_in_S = 1e-1; o->eps_in_A = 1e-6;
-    o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0;
+    o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0; o->mu_stop = 0.0;
     o->accept_relres = 1e-2;
     o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 60; o->inner_restart = 30;
     o->max_inner_S = 10;
@@ -1176,14 +1232,16 @@ void ot_options_default(ot_options *o) {
 
 const char *ot_last_error(void) { return g_last_error.c_str(); }
 
-int ot_kprof_select(int32_t kernel) {
+int ot_kprof_select(int32_t kernel, int32_t elem_bytes) {
     return guard([&] {
         OT_REQUIRE(kernel >= OT_KPROF_NONE && kernel <= OT_KPROF_SADDLE_PHI, OT_EINVAL, "unknown kernel id");
+        OT_REQUIRE(elem_bytes == 0 || elem_bytes == 4 || elem_bytes == 8, OT_EINVAL, "elem_bytes must be 0, 4 or 8");
         kprof::Prof &P = kprof::prof();
         std::lock_guard<std::mutex> lk(P.mu);
         for (size_t i = 0; i < P.used; ++i) OT_HIP(hipEventSynchronize(P.pool[i].second));
         P.used = 0;
         P.launches = 0; P.ms = 0.0; P.bytes = 0.0;
+        P.width = elem_bytes;
         P.sel = kernel;
     });
 }
@@ -1285,10 +1343,13 @@ int ot_state_set_options(ot_state *st, const ot_options *opt) {
         OT_REQUIRE((hipStream_t)opt->stream == st->stream, OT_EINVAL, "stream of a state cannot change");
         const int old_prec = st->opt.precision, old_inner = st->opt.inner_restart;
         st->opt = *opt;
-        if (old_prec != opt->precision || old_inner != opt->inner_restart) {
+        if (old_inner != opt->inner_restart) {     // inner basis size is fixed at allocation
             st->prec.reset();
             st->prec_kind = -1;
+            st->prec_alt.reset();
+            st->prec_alt_kind = -1;
         }
+        (void)old_prec;
         st->lin_valid = false;
     });
 }
@@ -1517,6 +1578,11 @@ static int dbg_vec(ot_state *st, const double *in, size_t nin, double *out, size
 int otbb_debug_schur_apply(ot_state *st, const double *z, double *out) {
     return dbg_vec(st, z, st ? st->mrho : 0, out, st ? st->mrho : 0,
                    [&](const double *a, double *b) { st->prec->schur_apply_d(st, a, b); });
+}
+
+int otbb_debug_tri_solve(ot_state *st, const double *r, double *x) {
+    return dbg_vec(st, r, st ? st->mrho : 0, x, st ? st->mrho : 0,
+                   [&](const double *a, double *b) { st->prec->tri_solve_d(st, a, b); });
 }
 
 int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double tol, int32_t maxit,

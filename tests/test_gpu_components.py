@@ -103,3 +103,64 @@ def test_laplace_solve(setup):
         worst = max(worst, np.linalg.norm(A @ x[k] - b[k]) / np.linalg.norm(b[k]))
     print(f"  laplace solve its {its.value} worst rel res {worst:.2e}", flush=True)
     assert worst < 10 * itol
+
+
+def _thomas_reference(d0, dl, du, r, K, nc):
+    """Host Thomas solve of the time-line tridiagonals with the library's
+    factorisation rule (a pivot that loses three digits to elimination is
+    replaced by the plain diagonal)."""
+    d0, dl, du, r = (a.reshape(K, nc) for a in (d0, dl, du, r))
+    inv, L, U = np.zeros((K, nc)), np.zeros((K, nc)), np.zeros((K, nc))
+    prev, prev_up = np.zeros(nc), np.zeros(nc)
+    for k in range(K):
+        d, l = d0[k].copy(), np.zeros(nc)
+        if k > 0:
+            ok = prev != 0.0
+            l = np.where(ok, dl[k] / np.where(ok, prev, 1.0), 0.0)
+            dd = d - l * prev_up
+            weak = ~(np.abs(dd) > 1e-3 * np.abs(d)) | ~np.isfinite(dd)
+            l = np.where(weak, 0.0, l)
+            d = np.where(weak, d, dd)
+        d = np.where(~(np.abs(d) > 0.0) | ~np.isfinite(d), 1.0, d)
+        u = du[k] if k + 1 < K else np.zeros(nc)
+        inv[k], L[k], U[k] = 1.0 / d, l, u
+        prev, prev_up = d, u
+    y, acc = np.zeros((K, nc)), np.zeros(nc)
+    for k in range(K):
+        acc = r[k] - L[k] * acc
+        y[k] = acc
+    x, xn = np.zeros((K, nc)), np.zeros(nc)
+    for k in reversed(range(K)):
+        xn = (y[k] - U[k] * xn) * inv[k]
+        x[k] = xn
+    return x.ravel()
+
+
+@pytest.mark.parametrize("K", [4, 64, 70, 130, 300])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 2e-4)])
+def test_time_line_solve(K, precision, tol):
+    """Time-line tridiagonal solve on the density cells: one wavefront per
+    cell with a scan over time (K <= 256: one full chunk, a ragged chunk,
+    several chunks) and the one-thread-per-cell recurrence (K = 300), both
+    against the host Thomas solve of the probed diagonals."""
+    n = 8
+    rng = np.random.default_rng(21 + K)
+    m = structured_mesh(n)
+    ri = rng.uniform(0.2, 2.0, m.n_coarse)
+    rf = rng.uniform(0.2, 2.0, m.n_coarse)
+    ri /= m.coarse_area @ ri
+    rf /= m.coarse_area @ rf
+    nf, nc = m.n_fine, m.n_coarse
+    print(f"[time-line solve {precision}] n={n} K={K}", flush=True)
+    st = ot.State(ot.Mesh.structured(n), ri, rf, K, precision=precision)
+    st.import_(rng.standard_normal((K + 1) * nf) * 0.2, rng.uniform(0.5, 2.0, K * nc),
+               rng.uniform(0.1, 1.0, K * nc), 0.3)
+    d0, dl, du = np.zeros(st.m_rho), np.zeros(st.m_rho), np.zeros(st.m_rho)
+    ot.check(ot.lib().otbb_debug_tri_diagonals(st._h, _dp(d0), _dp(dl), _dp(du)))
+    r = rng.standard_normal(st.m_rho)
+    x = np.zeros(st.m_rho)
+    ot.check(ot.lib().otbb_debug_tri_solve(st._h, _dp(r), _dp(x)))
+    ref = _thomas_reference(d0, dl, du, r, K, nc)
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    print(f"  time-line solve rel err {err:.2e}", flush=True)
+    assert err < tol
