@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # the CPU sample: the metric workload's marginal recipe on a reduced grid
 SAMPLE_N, SAMPLE_K = 24, 12
-KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde", "cheb_fine": "k_cheb_step<., 1>",
+KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 
 

@@ -60,6 +60,11 @@ int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double to
                            int32_t *iters);
 int otbb_debug_tri_diagonals(ot_state *st, double *d0, double *dl, double *du);
 int otbb_debug_tri_solve(ot_state *st, const double *r, double *x);
+/* Time levels per thread of the two time-blocked pseudo-Schur passes for
+ * FP32 (elem_bytes 4), FP64 (8) or both (0) operands (process-wide tuning
+ * knob; 0 levels = one level per thread; the defaults are 16 / 0 in FP32
+ * and 16 / 16 in FP64). */
+int otbb_debug_set_schur_blocking(int32_t elem_bytes, int32_t btilde_levels, int32_t out_levels);
 int otbb_debug_laplace_solve(ot_state *st, const double *b, double *x, double tol, int32_t maxit,
                              int32_t *iters);
 int otbb_debug_vcycle(ot_state *st, const double *b, double *x);

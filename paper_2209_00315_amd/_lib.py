@@ -102,6 +102,7 @@ SIGNATURES = {
     "otbb_debug_schur_levels": (C.c_int, [C.c_int32, C.c_int32, iptr, C.c_int32]),
     "otbb_debug_schur_apply": (C.c_int, [C.c_void_p, dptr, dptr]),
     "otbb_debug_tri_solve": (C.c_int, [C.c_void_p, dptr, dptr]),
+    "otbb_debug_set_schur_blocking": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
     "otbb_debug_schur_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
     "otbb_debug_tri_diagonals": (C.c_int, [C.c_void_p, dptr, dptr, dptr]),
     "otbb_debug_laplace_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),

@@ -466,6 +466,146 @@ __global__ void k_schur_out(MeshView m, int K, double dt, const T *__restrict__ 
     out[q] = (T)((double)sT[q] * at - (double)rhoT[q] * b);
 }
 
+// Time-blocked forms of passes 2 and 3: one thread per cell and kb
+// consecutive time levels.  The cell's stencil (indices and FP64 geometric
+// weights) is loaded once into registers instead of once per level, and the
+// operand of level k+1 that the next level reads as its level-k operand is
+// carried over instead of reloaded.  Used when the mesh's ELL widths fit the
+// register caps below (the structured grids do: w_f <= 4, w_o <= 2,
+// w_oc <= 3, w_r <= 6, w_cc <= 3); otherwise the per-level kernels above run.
+constexpr int kTbWF = 4, kTbWO = 2, kTbWOC = 4, kTbWR = 8, kTbWCC = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_schur_btilde_tb(MeshView m, int K, int kb, double dt, const T *__restrict__ z,
+                                                        const T *__restrict__ u, const T *__restrict__ g,
+                                                        T *__restrict__ v) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= m.nf) return;
+    const int k0 = blockIdx.y * kb, k1 = min(K + 1, k0 + kb);
+    int oc[kTbWO];
+    double ow[kTbWO];
+#pragma unroll
+    for (int t = 0; t < kTbWO; ++t) {
+        const int c = t < m.wo ? m.fo_c[t * m.nf + i] : -1;
+        oc[t] = c >= 0 ? c : 0;
+        ow[t] = c >= 0 ? m.fo_w[t * m.nf + i] / dt : 0.0;
+    }
+    int fe[kTbWF], fn[kTbWF];
+    double fw[kTbWF];
+#pragma unroll
+    for (int t = 0; t < kTbWF; ++t) {
+        const int e = t < m.wf ? m.cf_edge[t * m.nf + i] : -1;
+        fe[t] = e >= 0 ? e : 0;
+        fn[t] = e >= 0 ? m.cf_nb[t * m.nf + i] : i;
+        double w = 0.0;
+        if (e >= 0) {
+            const bool isK = m.eK[e] == i;
+            const double side = isK ? m.elam[e] : 1.0 - m.elam[e];
+            w = (isK ? 1.0 : -1.0) * side * m.eW[e] * m.einvd[e];
+        }
+        fw[t] = w;
+    }
+    const double inva = 1.0 / m.a[i];
+    // z at level k-1 for the first level of the block
+    T zp[kTbWO];
+#pragma unroll
+    for (int t = 0; t < kTbWO; ++t) zp[t] = k0 >= 1 ? z[(size_t)(k0 - 1) * m.nc + oc[t]] : (T)0;
+    for (int k = k0; k < k1; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < kTbWO; ++t) {
+            const T zc = k < K ? z[(size_t)k * m.nc + oc[t]] : (T)0;
+            acc += ow[t] * ((double)zc - (double)zp[t]);
+            zp[t] = zc;
+        }
+        const T *uk = u + (size_t)k * m.nf;
+        const T *gk = g + (size_t)k * m.ne;
+        const double ui = (double)uk[i];
+#pragma unroll
+        for (int t = 0; t < kTbWF; ++t) acc += fw[t] * (double)gk[fe[t]] * (ui - (double)uk[fn[t]]);
+        v[(size_t)k * m.nf + i] = (T)(acc * inva);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_schur_out_tb(MeshView m, int K, int kb, double dt, const T *__restrict__ z,
+                                                     const T *__restrict__ v, const T *__restrict__ g,
+                                                     const T *__restrict__ wc, const T *__restrict__ rhoT,
+                                                     const T *__restrict__ sT, T *__restrict__ out) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= m.nc) return;
+    const int k0 = blockIdx.y * kb, k1 = min(K, k0 + kb);
+    int ce[kTbWCC], cn[kTbWCC];
+    bool cv[kTbWCC];
+#pragma unroll
+    for (int t = 0; t < kTbWCC; ++t) {
+        const int e = t < m.wcc ? m.cc_edge[t * m.nc + j] : -1;
+        cv[t] = e >= 0;
+        ce[t] = cv[t] ? e : 0;
+        cn[t] = cv[t] ? m.cc_nb[t * m.nc + j] : j;
+    }
+    int of[kTbWOC];
+    double ow[kTbWOC];
+#pragma unroll
+    for (int t = 0; t < kTbWOC; ++t) {
+        const int f = t < m.woc ? m.co_f[t * m.nc + j] : -1;
+        of[t] = f >= 0 ? f : 0;
+        ow[t] = f >= 0 ? m.co_w[t * m.nc + j] / dt : 0.0;
+    }
+    int re[kTbWR], rk[kTbWR], rl[kTbWR];
+    double rw[kTbWR];
+#pragma unroll
+    for (int t = 0; t < kTbWR; ++t) {
+        const int e = t < m.wr ? m.cr_e[t * m.nc + j] : -1;
+        re[t] = e >= 0 ? e : 0;
+        rk[t] = e >= 0 ? m.eK[e] : 0;
+        rl[t] = e >= 0 ? m.eL[e] : 0;
+        rw[t] = e >= 0 ? 0.5 * m.cr_w[t * m.nc + j] * m.einvd[e] : 0.0;
+    }
+    // operands at level k0 (v and g have K+1 levels)
+    T vo[kTbWOC], vk[kTbWR], vl[kTbWR], gg0[kTbWR];
+    {
+        const T *v0 = v + (size_t)k0 * m.nf;
+        const T *g0 = g + (size_t)k0 * m.ne;
+#pragma unroll
+        for (int t = 0; t < kTbWOC; ++t) vo[t] = v0[of[t]];
+#pragma unroll
+        for (int t = 0; t < kTbWR; ++t) {
+            vk[t] = v0[rk[t]];
+            vl[t] = v0[rl[t]];
+            gg0[t] = g0[re[t]];
+        }
+    }
+    for (int k = k0; k < k1; ++k) {
+        const T *zk = z + (size_t)k * m.nc;
+        const T *wck = wc + (size_t)k * m.nce;
+        const T *v1 = v + (size_t)(k + 1) * m.nf;
+        const T *g1 = g + (size_t)(k + 1) * m.ne;
+        const double zj = (double)zk[j];
+        double at = 0.0;
+#pragma unroll
+        for (int t = 0; t < kTbWCC; ++t)
+            if (cv[t]) at += (double)wck[ce[t]] * (zj - (double)zk[cn[t]]);
+        double b = 0.0;
+#pragma unroll
+        for (int t = 0; t < kTbWOC; ++t) {
+            const T x1 = v1[of[t]];
+            b += ow[t] * ((double)x1 - (double)vo[t]);
+            vo[t] = x1;
+        }
+#pragma unroll
+        for (int t = 0; t < kTbWR; ++t) {
+            const T k1v = v1[rk[t]], l1v = v1[rl[t]], g1v = g1[re[t]];
+            b += rw[t] * ((double)gg0[t] * ((double)vk[t] - (double)vl[t]) + (double)g1v * ((double)k1v - (double)l1v));
+            vk[t] = k1v;
+            vl[t] = l1v;
+            gg0[t] = g1v;
+        }
+        const size_t q = (size_t)k * m.nc + j;
+        out[q] = (T)((double)sT[q] * at - (double)rhoT[q] * b);
+    }
+}
+
 // probe vector: 1 at (k, j) with k % 3 == tc and color[j] == c
 template <typename T>
 __global__ void k_probe(int nc, const int *__restrict__ color, int tc, int c, T *__restrict__ p) {

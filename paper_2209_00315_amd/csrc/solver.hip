@@ -63,6 +63,13 @@ Ev take_slot(double bytes) {
 // inner_restart are validated against it); sizes every Krylov scratch.
 constexpr int kMaxBasis = 401;
 constexpr int kMultidotBlocks = 512;
+// time levels per thread of the two time-blocked pseudo-Schur passes
+// (M^-1 B~ z, output) for FP32 [0] and FP64 [1] operands; 0 selects the
+// one-level-per-thread kernels.  Measured at 256^2, K = 64: blocking by 16
+// cuts the FP32 M^-1 B~ z pass from 72 to 28 us and the FP64 passes from
+// 83 / 103 to 53 / 65 us, while the FP32 output pass is fastest unblocked
+// (76 us; blocked 92-128 us, fewer independent gathers in flight).
+static int g_schur_tb[2][2] = {{16, 0}, {16, 16}};
 // longest time line the wavefront-scan tridiagonal solve handles
 constexpr int kTriScanMaxK = 64 * kern::kTriScanChunks;
 
@@ -529,22 +536,37 @@ struct BBPrec : PrecBase {
         k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, z, uT);
         const double b = sizeof(T), S1 = K + 1;
         const MeshHost &h = m->h;
+        // time-blocked passes (levels per thread; 0 = per-level kernels) when
+        // the cell stencils fit their register caps
+        const bool fits = h.wf <= kTbWF && h.wo <= kTbWO && h.woc <= kTbWOC && h.wr <= kTbWR && h.wcc <= kTbWCC;
+        const int *tbl = g_schur_tb[sizeof(T) == 8 ? 1 : 0];
+        const int tb_btilde = fits ? tbl[0] : 0, tb_out = fits ? tbl[1] : 0;
         {
             // z, u, g, v once; overlap, cell-edge and edge geometry once
             const double bytes = b * ((double)K * nc + 2.0 * S1 * nf + S1 * ne) +
                                  12.0 * h.wo * nf + 8.0 * h.wf * nf + 28.0 * ne + 8.0 * nf;
             const kprof::Ev ev = kprof::take(OT_KPROF_SCHUR_BTILDE, sizeof(T), bytes);
-            hipExtLaunchKernelGGL(k_schur_btilde<T>, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K,
-                                  st->dt, z, (const T *)uT.p, (const T *)g.p, vT.p);
+            if (tb_btilde > 0)
+                hipExtLaunchKernelGGL(k_schur_btilde_tb<T>, dim3(ceil_div(nf, BS), ceil_div(K + 1, tb_btilde)),
+                                      dim3(BS), 0, s, ev.a, ev.b, 0, mv, K, tb_btilde, st->dt, z, (const T *)uT.p,
+                                      (const T *)g.p, vT.p);
+            else
+                hipExtLaunchKernelGGL(k_schur_btilde<T>, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K,
+                                      st->dt, z, (const T *)uT.p, (const T *)g.p, vT.p);
         }
         {
             // z, v, g, w~, rho, s, out once; coarse-cell geometry once
             const double bytes = b * (4.0 * K * nc + S1 * nf + S1 * ne + (double)K * nce) + 8.0 * h.wcc * nc +
                                  12.0 * h.woc * nc + 12.0 * h.wr * nc + 16.0 * ne;
             const kprof::Ev ev = kprof::take(OT_KPROF_SCHUR_OUT, sizeof(T), bytes);
-            hipExtLaunchKernelGGL(k_schur_out<T>, grid2(nc, K), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K, st->dt, z,
-                                  (const T *)vT.p, (const T *)g.p, (const T *)wc.p, (const T *)rhoT.p,
-                                  (const T *)sT.p, out);
+            if (tb_out > 0)
+                hipExtLaunchKernelGGL(k_schur_out_tb<T>, dim3(ceil_div(nc, BS), ceil_div(K, tb_out)), dim3(BS),
+                                      0, s, ev.a, ev.b, 0, mv, K, tb_out, st->dt, z, (const T *)vT.p,
+                                      (const T *)g.p, (const T *)wc.p, (const T *)rhoT.p, (const T *)sT.p, out);
+            else
+                hipExtLaunchKernelGGL(k_schur_out<T>, grid2(nc, K), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K, st->dt,
+                                      z, (const T *)vT.p, (const T *)g.p, (const T *)wc.p, (const T *)rhoT.p,
+                                      (const T *)sT.p, out);
         }
     }
 
@@ -1578,6 +1600,19 @@ static int dbg_vec(ot_state *st, const double *in, size_t nin, double *out, size
 int otbb_debug_schur_apply(ot_state *st, const double *z, double *out) {
     return dbg_vec(st, z, st ? st->mrho : 0, out, st ? st->mrho : 0,
                    [&](const double *a, double *b) { st->prec->schur_apply_d(st, a, b); });
+}
+
+int otbb_debug_set_schur_blocking(int32_t elem_bytes, int32_t btilde_levels, int32_t out_levels) {
+    return guard([&] {
+        OT_REQUIRE(btilde_levels >= 0 && btilde_levels <= 64 && out_levels >= 0 && out_levels <= 64, OT_EINVAL,
+                   "levels per thread must be in [0, 64]");
+        OT_REQUIRE(elem_bytes == 0 || elem_bytes == 4 || elem_bytes == 8, OT_EINVAL, "elem_bytes must be 0, 4 or 8");
+        for (int r = 0; r < 2; ++r) {
+            if (elem_bytes != 0 && elem_bytes != (r ? 8 : 4)) continue;
+            g_schur_tb[r][0] = btilde_levels;
+            g_schur_tb[r][1] = out_levels;
+        }
+    });
 }
 
 int otbb_debug_tri_solve(ot_state *st, const double *r, double *x) {

@@ -164,3 +164,43 @@ def test_time_line_solve(K, precision, tol):
     err = np.abs(x - ref).max() / np.abs(ref).max()
     print(f"  time-line solve rel err {err:.2e}", flush=True)
     assert err < tol
+
+
+@pytest.mark.parametrize("levels", [0, 1, 8, 16])
+@pytest.mark.parametrize("K", [4, 8, 12, 17])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_schur_operator_time_blocks(K, precision, tol, levels):
+    """Pseudo-Schur operator through the time-blocked passes (levels per
+    thread; 0 = per-level kernels): K below, at, and past one block, with a
+    ragged last block."""
+    w = 4 if precision == "mixed" else 8
+    ot.check(ot.lib().otbb_debug_set_schur_blocking(w, levels, levels))
+    try:
+        _schur_blocks_case(K, precision, tol, levels)
+    finally:
+        ot.check(ot.lib().otbb_debug_set_schur_blocking(w, 16, 0 if w == 4 else 16))
+
+
+def _schur_blocks_case(K, precision, tol, levels):
+    n = 8
+    rng = np.random.default_rng(40 + K)
+    m = structured_mesh(n)
+    ri = rng.uniform(0.2, 2.0, m.n_coarse)
+    rf = rng.uniform(0.2, 2.0, m.n_coarse)
+    ri /= m.coarse_area @ ri
+    rf /= m.coarse_area @ rf
+    prob = Problem(m, K, ri, rf)
+    phi = rng.standard_normal((K + 1, prob.nf)) * 0.2
+    rho = rng.uniform(0.5, 2.0, (K, prob.nc))
+    s = rng.uniform(0.1, 1.0, (K, prob.nc))
+    print(f"[schur blocks {precision}] n={n} K={K} levels={levels}", flush=True)
+    st = ot.State(ot.Mesh.structured(n), ri, rf, K, precision=precision)
+    st.import_(phi.ravel(), rho.ravel(), s.ravel(), 0.3)
+    S = pseudo_schur(prob, phi, rho, s)
+    z = rng.standard_normal(st.m_rho)
+    out = np.zeros(st.m_rho)
+    ot.check(ot.lib().otbb_debug_schur_apply(st._h, _dp(z), _dp(out)))
+    ref = S @ z
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"  schur apply rel err {err:.2e}", flush=True)
+    assert err < tol
