@@ -26,6 +26,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # the CPU sample: the metric workload's marginal recipe on a reduced grid
 SAMPLE_N, SAMPLE_K = 24, 12
+COPY_BYTES = 1 << 30          # reference copy of the counter loop: 1 GiB read, 1 GiB written
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# `bench.py --counter-loop 20` (KiB per dispatch), scaled by what the same
+# counters read for the 1 GiB reference copy (fetch x2.0000, write x1.0000);
+# profiles/k_schur_out_256x256_K64_traffic.md.  Valid only for the kernel
+# version those runs measured, on the 256 x 256, K = 64 workload.
+TRAFFIC_BYTES = {("schur_out", 3): 72822.12 * 1024 * 1.99995 + 8192.0 * 1024 * 1.0}
 KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 
@@ -46,6 +53,9 @@ def parse():
                    help="also solve the CPU sample on the GPU (adds small launches to a profile)")
     p.add_argument("--verbose", type=int, default=0)
     p.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    p.add_argument("--counter-loop", type=int, default=0,
+                   help="only run N pseudo-Schur applications of the workload's mixed state and N plain "
+                        "copies of a known size (for hardware-counter runs), then exit")
     return p.parse_args()
 
 
@@ -76,6 +86,31 @@ def run_cpu_baseline():
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
+def counter_loop(a, ot, otinputs, torch, dev):
+    """Hardware-counter workload: the mixed state of the benchmark problem after
+    one Newton step, N applications of its pseudo-Schur operator (one launch of
+    each pass per application), then N device copies of COPY_BYTES."""
+    import ctypes as C
+
+    import numpy as np
+
+    n, K, ri, rf = otinputs.config_marginals(a.config)
+    mesh = ot.Mesh.structured(n)
+    st = ot.State(mesh, ri, rf, K, precision="mixed")
+    st.newton_step(raise_on_error=False)
+    z = np.random.default_rng(0).standard_normal(st.m_rho)
+    out = np.zeros(st.m_rho)
+    dp = C.POINTER(C.c_double)
+    for _ in range(a.counter_loop):
+        ot.check(ot.lib().otbb_debug_schur_apply(st._h, z.ctypes.data_as(dp), out.ctypes.data_as(dp)))
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(a.counter_loop):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_loop": a.counter_loop, "copy_bytes": COPY_BYTES, "m_rho": st.m_rho}), flush=True)
+
+
 def main():
     a = parse()
     if a.cpu_sample_only:
@@ -91,6 +126,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda")
+    if a.counter_loop > 0:
+        counter_loop(a, ot, otinputs, torch, dev)
+        return
 
     mu_stop = a.mu_stop if a.mu_stop is not None else (8e-3 if a.config == 3 else 0.0)
 
@@ -171,7 +209,8 @@ def main():
         "cost": results[-1]["cost"],
         "gap": st.gap,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": TRAFFIC_BYTES.get((a.kernel, a.config)), "traffic_unit": "bytes per launch",
                      "kernel": f"{KERNEL_NAMES.get(a.kernel, a.kernel)} (FP32)", "launches": launches,
                      "avg_us": 1000.0 * kms / launches if launches else None,
                      "bytes_per_launch": kbytes / launches if launches else None},

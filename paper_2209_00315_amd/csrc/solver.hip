@@ -876,6 +876,7 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
     double res = beta;
     std::vector<double> h(m + 1), hist;
     bool stop = false;
+    const double beta0 = beta;
     while (its < maxit) {
         k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, st->V.p, 1.0 / beta, st->V.p);
         G.reset(beta);
@@ -895,10 +896,12 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
             if (hn > 0) k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, wn, 1.0 / hn, wn);
             if (st->opt.verbose > 1) fprintf(stderr, "    fgmres it %d res %.3e target %.3e\n", its, res, tol_abs);
             hist.push_back(res);
-            // plateau: no halving over the last 40 iterations (after 80); the
-            // residual has met the rounding floor of the operator or the
-            // preconditioner no longer helps, and the caller's retry decides
-            const bool stalled = its >= 80 && res > 0.5 * hist[its - 41];
+            // plateau: no halving over the last 40 iterations (after 80) once
+            // the residual is already within accept_relres of the initial
+            // one, where the step is taken anyway: near a converged Newton
+            // iterate the residual meets the rounding floor of the operator
+            // well above eps_out |b|, and the cap would only add time
+            const bool stalled = its >= 80 && res > 0.5 * hist[its - 41] && res <= st->opt.accept_relres * beta0;
             if (res <= tol_abs || hn == 0.0 || stalled) { stop = stalled; ++j; break; }
         }
         std::vector<double> y = G.solve(j);
@@ -992,9 +995,10 @@ static int newton_step(ot_state *st, double *res_before) {
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
     int its = solve_newton_system(st, fn);
-    if (!st->last_converged) {
-        // retry once with the FP64 preconditioner, inner tolerances / 10 and
-        // the pseudo-Schur cap lifted to the general inner cap
+    if (!st->last_converged && !(st->last_relres <= st->opt.accept_relres)) {
+        // a step that would be rejected: retry once with the FP64
+        // preconditioner, inner tolerances / 10 and the pseudo-Schur cap
+        // lifted to the general inner cap
         const ot_options saved = st->opt;
         const int its1 = st->last_iters;
         const double rr1 = st->last_relres;
