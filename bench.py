@@ -32,7 +32,7 @@ COPY_BYTES = 1 << 30          # reference copy of the counter loop: 1 GiB read, 
 # counters read for the 1 GiB reference copy (fetch x2.0000, write x1.0000);
 # profiles/k_schur_out_256x256_K64_traffic.md.  Valid only for the kernel
 # version those runs measured, on the 256 x 256, K = 64 workload.
-TRAFFIC_BYTES = {("schur_out", 3): 72822.12 * 1024 * 1.99995 + 8192.0 * 1024 * 1.0}
+TRAFFIC_BYTES = {("schur_out", 3): 73838.51 * 1024 * 1.99995 + 8192.0 * 1024 * 1.00000}
 KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 

@@ -24,6 +24,8 @@ struct MeshView {
     int nf, nc, ne, nce, wf, wo, woc, wr, wcc;
     const double *a, *ac, *elam, *etw, *eW, *einvd, *elen, *cetw, *celam, *fo_w, *co_w, *cr_w;
     const int *eK, *eL, *erK, *erL, *ceI, *ceJ, *cf_edge, *cf_nb, *fo_c, *co_f, *cr_e, *cc_edge, *cc_nb;
+    const int *cr_k, *cr_l;     // R_T slots resolved: potential cells of the edge
+    const double *cr_g;         // R_T slots resolved: 0.5 cr_w / d_e
 };
 
 struct StateView {
@@ -454,15 +456,14 @@ __global__ void k_schur_out(MeshView m, int K, double dt, const T *__restrict__ 
         if (f < 0) break;
         b += m.co_w[t * m.nc + j] * ((double)v1[f] - (double)v0[f]) / dt;
     }
-    double gg = 0.0;
     for (int t = 0; t < m.wr; ++t) {
-        const int e = m.cr_e[t * m.nc + j];
+        const int q = t * m.nc + j;
+        const int e = m.cr_e[q];
         if (e < 0) break;
-        const int eK = m.eK[e], eL = m.eL[e];
-        gg += m.cr_w[t * m.nc + j] * m.einvd[e] *
-              ((double)g0[e] * ((double)v0[eK] - (double)v0[eL]) + (double)g1[e] * ((double)v1[eK] - (double)v1[eL]));
+        const int eK = m.cr_k[q], eL = m.cr_l[q];
+        b += m.cr_g[q] *
+             ((double)g0[e] * ((double)v0[eK] - (double)v0[eL]) + (double)g1[e] * ((double)v1[eK] - (double)v1[eL]));
     }
-    b += 0.5 * gg;
     out[q] = (T)((double)sT[q] * at - (double)rhoT[q] * b);
 }
 
@@ -556,11 +557,12 @@ __global__ void __launch_bounds__(BS) k_schur_out_tb(MeshView m, int K, int kb, 
     double rw[kTbWR];
 #pragma unroll
     for (int t = 0; t < kTbWR; ++t) {
-        const int e = t < m.wr ? m.cr_e[t * m.nc + j] : -1;
+        const int q = t * m.nc + j;
+        const int e = t < m.wr ? m.cr_e[q] : -1;
         re[t] = e >= 0 ? e : 0;
-        rk[t] = e >= 0 ? m.eK[e] : 0;
-        rl[t] = e >= 0 ? m.eL[e] : 0;
-        rw[t] = e >= 0 ? 0.5 * m.cr_w[t * m.nc + j] * m.einvd[e] : 0.0;
+        rk[t] = e >= 0 ? m.cr_k[q] : 0;
+        rl[t] = e >= 0 ? m.cr_l[q] : 0;
+        rw[t] = e >= 0 ? m.cr_g[q] : 0.0;
     }
     // operands at level k0 (v and g have K+1 levels)
     T vo[kTbWOC], vk[kTbWR], vl[kTbWR], gg0[kTbWR];

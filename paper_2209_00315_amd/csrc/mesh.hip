@@ -523,6 +523,18 @@ void mesh_finalize(ot_mesh *m) {
     m->ceI.upload(h.ceI, s); m->ceJ.upload(h.ceJ, s);
     m->cf_edge.upload(h.cf_edge, s); m->cf_nb.upload(h.cf_nb, s);
     m->fo_c.upload(h.fo_c, s); m->co_f.upload(h.co_f, s); m->cr_e.upload(h.cr_e, s);
+    {
+        std::vector<int> ck(h.cr_e.size(), 0), cl(h.cr_e.size(), 0);
+        std::vector<double> cg(h.cr_e.size(), 0.0);
+        for (size_t q = 0; q < h.cr_e.size(); ++q) {
+            const int e = h.cr_e[q];
+            if (e < 0) continue;
+            ck[q] = h.eK[e];
+            cl[q] = h.eL[e];
+            cg[q] = 0.5 * h.cr_w[q] * invd[e];
+        }
+        m->cr_k.upload(ck, s); m->cr_l.upload(cl, s); m->cr_g.upload(cg, s);
+    }
     m->cc_edge.upload(h.cc_edge, s); m->cc_nb.upload(h.cc_nb, s);
     m->color.upload(h.color, s);
     m->slv.clear();

@@ -83,6 +83,12 @@ struct ot_mesh {
     otbb::DBuf<double> a, ac, elam, etw, eW, einvd, elen, cetw, celam, fo_w, co_w, cr_w;
     otbb::DBuf<int> eK, eL, erK, erL, ceI, ceJ, cf_edge, cf_nb, fo_c, co_f, cr_e, cc_edge, cc_nb;
     otbb::DBuf<int> color;
+    // R_T stencil of each coarse cell resolved once at setup, same ELL slots
+    // as cr_e: the edge's two potential cells and 0.5 cr_w / d_e, so the
+    // pseudo-Schur output pass reads them coalesced instead of through the
+    // edge index
+    otbb::DBuf<int> cr_k, cr_l;
+    otbb::DBuf<double> cr_g;
     std::vector<otbb::MGLevelDev> lv;
     std::vector<otbb::SLevelDev> slv;
     double area = 0.0;                 // |Omega| = sum of coarse areas

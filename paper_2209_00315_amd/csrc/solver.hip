@@ -96,6 +96,7 @@ MeshView mesh_view(const ot_mesh *m) {
     v.eK = m->eK; v.eL = m->eL; v.erK = m->erK; v.erL = m->erL; v.ceI = m->ceI; v.ceJ = m->ceJ;
     v.cf_edge = m->cf_edge; v.cf_nb = m->cf_nb; v.fo_c = m->fo_c; v.co_f = m->co_f; v.cr_e = m->cr_e;
     v.cc_edge = m->cc_edge; v.cc_nb = m->cc_nb;
+    v.cr_k = m->cr_k; v.cr_l = m->cr_l; v.cr_g = m->cr_g;
     return v;
 }
 
@@ -557,7 +558,7 @@ struct BBPrec : PrecBase {
         {
             // z, v, g, w~, rho, s, out once; coarse-cell geometry once
             const double bytes = b * (4.0 * K * nc + S1 * nf + S1 * ne + (double)K * nce) + 8.0 * h.wcc * nc +
-                                 12.0 * h.woc * nc + 12.0 * h.wr * nc + 16.0 * ne;
+                                 12.0 * h.woc * nc + 20.0 * h.wr * nc;
             const kprof::Ev ev = kprof::take(OT_KPROF_SCHUR_OUT, sizeof(T), bytes);
             if (tb_out > 0)
                 hipExtLaunchKernelGGL(k_schur_out_tb<T>, dim3(ceil_div(nc, BS), ceil_div(K, tb_out)), dim3(BS),
