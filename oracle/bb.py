@@ -12,7 +12,7 @@ Sec. 4.4.3: the dual Schur complement is approximated through the commutator
 followed by the block-triangular back-substitution A x = c - B^T P^T y over
 the K+1 independent Laplacians.
 
-Readings (listed in DESIGN.md):
+Readings where the paper is silent or its formula does not type-check:
   * A~^k is the positive coarse Laplacian -div' Diag(R'_E rho^k) grad';
   * B~ = -Omega D~_t^T + G_f D_x J H^T with G_f^k = R_Tf Diag(grad phi^k) and
     J = M^-1 Omega: the fine operator M (d/dt + grad phi . grad) composed with

@@ -6,7 +6,7 @@ dt = 1/(K+1), rho^0 = rho_in and rho^{K+1} = rho_f (Sec. 2.2).  Arrays are
 slice-major: phi has shape (K+1, n_fine), rho and s have shape (K, n_coarse);
 python index k-1 holds the paper's level k.
 
-Readings where the paper is silent or inconsistent (listed in the design doc):
+Readings where the paper is silent or inconsistent:
   * the time-difference term of F_rho uses Omega^T = J^T M (the transpose of the
     term of F_phi); the printed M' J^T differs from it by the child count and
     would break the symmetry of the Jacobian that Sec. 3 states;

@@ -43,7 +43,35 @@ def test_option_defaults():
     assert (o.tol, o.eps_out, o.eps_in_S) == (1e-6, 1e-5, 1e-1)
     assert (o.mu0, o.mu_factor, o.frac_to_boundary) == (1.0, 0.2, 0.99)
     assert (o.max_fgmres, o.max_inner, o.max_inner_S, o.max_newton) == (400, 200, 10, 60)
+    assert (o.eps_in_A, o.restart, o.inner_restart, o.accept_relres) == (1e-6, 400, 30, 1e-2)
+    assert (o.mu_stop, o.final_tol, o.step_rule) == (0.0, 0.0, 0)
     assert o.precision == ot.OT_MIXED and o.mem_kind == ot.OT_HOST
+
+
+def test_kernel_timing_selection_codes():
+    ot, L = _lib()
+    assert L.ot_kprof_select(99, 0) == ot.OT_EINVAL
+    assert L.ot_kprof_select(1, 3) == ot.OT_EINVAL
+    ot.kprof_select("schur_out", 4)
+    assert ot.kprof_read() == (0, 0.0, 0.0)        # nothing launched yet
+    ot.kprof_select("none")
+
+
+def test_schur_blocking_knob_codes():
+    ot, L = _lib()
+    assert L.otbb_debug_set_schur_blocking(5, 1, 1) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_blocking(4, 65, 0) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_blocking(4, 16, 0) == 0     # the defaults
+    assert L.otbb_debug_set_schur_blocking(8, 16, 16) == 0
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
 
 
 def _arrays(n, cart):
