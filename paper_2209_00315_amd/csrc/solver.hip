@@ -424,7 +424,6 @@ struct BBPrec : PrecBase {
         hipStream_t s = st->stream;
         for (int l = 1; l < nsl; ++l) {
             const SLevelDev &P = m->slv[l - 1], &L = m->slv[l];
-            const size_t nk = (size_t)K * L.n;
             k_fill<T><<<grid1(sv[l].n), BS, 0, s>>>(sv[l], sv[l].n, (T)0);
             for (int tc = 0; tc < std::min(3, K); ++tc)
                 for (int c = 0; c < L.ncolor; ++c) {
@@ -435,7 +434,6 @@ struct BBPrec : PrecBase {
                 }
             k_sdiag<T><<<grid2(L.n, K), BS, 0, s>>>(slview(m, l), K, sv[l], sd0, sdl, sdu);
             k_tri_factor<T><<<grid1(L.n, 1 << 20), BS, 0, s>>>(L.n, K, sd0, sdl, sdu, sinv[l], slm[l], sup[l]);
-            (void)nk;
         }
     }
 
@@ -990,12 +988,11 @@ static int newton_step(ot_state *st, double *res_before) {
     dim3 gc = grid2(nc, K);
     k_newton_rhs<<<gc, BS, 0, s>>>(mv, sv, st->F, st->rhs, st->gt, st->red.part, st->nphi, st->mrho);
     st->lin_valid = false;
-    st->acc.seconds_setup += 0.0;
     double ts = now_s();
     linearize(st);
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
-    int its = solve_newton_system(st, fn);
+    solve_newton_system(st, fn);
     if (!st->last_converged && !(st->last_relres <= st->opt.accept_relres)) {
         // a step that would be rejected: retry once with the FP64
         // preconditioner, inner tolerances / 10 and the pseudo-Schur cap
@@ -1008,7 +1005,7 @@ static int newton_step(ot_state *st, double *res_before) {
         st->opt.eps_in_A = 0.1 * saved.eps_in_A;
         st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
         linearize(st);
-        its += solve_newton_system(st, fn);
+        solve_newton_system(st, fn);
         st->acc.linear_systems--;              // one Newton system, two attempts
         if (st->opt.verbose)
             fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1,
@@ -1027,7 +1024,6 @@ static int newton_step(ot_state *st, double *res_before) {
         }
         rc = OT_ELINSOLVE;
     }
-    (void)its;
     // ds and the step length
     double *drho = st->sol.p + st->nphi;
     int nblk = grid1(st->mrho);
@@ -1368,7 +1364,7 @@ int ot_state_set_options(ot_state *st, const ot_options *opt) {
         OT_REQUIRE(st && opt, OT_EINVAL, "null argument");
         check_options(*opt);
         OT_REQUIRE((hipStream_t)opt->stream == st->stream, OT_EINVAL, "stream of a state cannot change");
-        const int old_prec = st->opt.precision, old_inner = st->opt.inner_restart;
+        const int old_inner = st->opt.inner_restart;
         st->opt = *opt;
         if (old_inner != opt->inner_restart) {     // inner basis size is fixed at allocation
             st->prec.reset();
@@ -1376,7 +1372,6 @@ int ot_state_set_options(ot_state *st, const ot_options *opt) {
             st->prec_alt.reset();
             st->prec_alt_kind = -1;
         }
-        (void)old_prec;
         st->lin_valid = false;
     });
 }
