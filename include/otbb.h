@@ -168,7 +168,9 @@ int  ot_mesh_sizes(const ot_mesh *mesh, int32_t *n_fine, int32_t *n_coarse,
 
 /*
  * Full interior-point solve (Sec. 2.4): mu_l = mu0 mu_factor^l, inexact
- * Newton until |F_mu| <= tol at each mu, stop after the first mu < tol.
+ * Newton until |F_mu| <= tol at each mu (final_tol at the last one), stop
+ * after the first mu < tol, or after the first mu <= opt->mu_stop when that
+ * is positive.
  * Outputs: rho_out [K n_coarse], phi_out [(K+1) n_fine] shifted so that
  * sum_k a^T phi^k = 0, cost_out = discrete kinetic energy.  Any output
  * pointer may be NULL.  stats may be NULL.
@@ -180,9 +182,10 @@ int  ot_solve(const ot_mesh *mesh, const double *rho_in, const double *rho_f,
               double *rho_out, double *phi_out, double *cost_out, ot_stats *stats);
 
 /*
- * Solve nprob independent problems (meshes and K may differ) with one
- * device state per problem, interleaving their kernels on the same stream.
- * Arrays of pointers have nprob entries; costs[nprob]; stats[nprob] or NULL.
+ * Solve nprob independent problems (meshes and K may differ), one after
+ * another on opt->stream, each with its own state as in ot_solve.  Arrays
+ * of pointers have nprob entries; costs[nprob]; stats[nprob] or NULL.  All
+ * members are attempted; the return value is the first member's error.
  */
 int  ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes,
                       const double *const *rho_in, const double *const *rho_f,
@@ -213,9 +216,12 @@ int  ot_residual(ot_state *st, double *F, double *nrm);
  * on the projected system with the BB preconditioner, recovery of
  * (delta phi, delta rho, delta s) (Sec. 4.4.1-4.4.2, Sec. 3.1), positivity
  * line search with the step fraction, update, per-slice renormalisation of
- * rho.  *res_norm (may be NULL) receives |F_mu| before the step.
- * Errors: OT_ELINSOLVE (step still taken if the residual dropped below 1e-2
- * of the right-hand side), OT_EDEVICE.
+ * rho.  *res_norm (may be NULL) receives |F_mu| before the step.  When
+ * FGMRES ends above eps_out: at most accept_relres the step is taken and
+ * OT_ELINSOLVE returned (counted as a failure); above it the system is
+ * solved again with the FP64 preconditioner and inner tolerances / 10, and
+ * if that also ends above accept_relres the state is left unchanged.
+ * Errors: OT_ELINSOLVE, OT_EDEVICE.
  */
 int  ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm);
 
@@ -231,8 +237,9 @@ int  ot_apply_saddle(ot_state *st, const double *x, double *y);
  * (Diag(s) A~ - Diag(rho) B M^-1 B~) w = -Diag(rho) P r_rho, then
  * z_rho = P^T M'^-1 A~ w, then the K+1 Laplacian solves
  * A^k z_phi^k = (r_phi - B^T z_rho)^k projected to zero sum; z_phi^k is
- * returned with zero sum.  Inner tolerances come from the state's options;
- * set eps_in_S and eps_in_A to ~1e-13 for (near-)exact inner solves.
+ * returned with zero sum.  Inner tolerances and caps come from the state's
+ * options; for (near-)exact inner solves set eps_in_S and eps_in_A to ~1e-13
+ * and raise max_inner_S and max_inner.
  */
 int  ot_apply_schur_prec(ot_state *st, const double *r, double *z);
 
