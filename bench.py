@@ -139,7 +139,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = ot.solve(mesh, ri_d, rf_d, K, tol=1e-6, device=True, precision=precision, verbose=a.verbose,
-                       mu_stop=mu_stop)
+                       mu_stop=mu_stop, raise_on_error=False)
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
@@ -198,6 +198,7 @@ def main():
                    "continuation": (f"mu = 0.2^l from 1 down to {mu_stop:g}, each mu solved to |F| <= 1e-6"
                                     if mu_stop > 0 else "mu = 0.2^l from 1 down to the first mu below 1e-6")},
         "time_to_tol_s": T / a.steps,
+        "rc": [r["rc"] for r in results],          # library status of each timed solve (0 = converged)
         "mu_final": st.mu,
         "linear_systems": systems // a.steps,
         "outer_per_linear_system": its / max(systems, 1),
