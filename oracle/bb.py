@@ -29,11 +29,18 @@ Readings where the paper is silent or its formula does not type-check:
   * the time shift enters the potential at level k as dt * sum_{i<k} delta
     lambda^i (the shift has K components, one per density level).
 
-Pins (tests/test_oracle_bb.py): P^2 = P, E' M' E'^T = |Omega| I, the kernel
-relations of Sec. 3 and Sec. 4.4.2, two-step convergence of GMRES with the
-ideal Schur complement, the commutator being small for a translation and
-large when B~ is misread, and projected solve + recovery agreeing with the
-grounded direct solve of J_s.
+Pins (tests/test_oracle_bb.py, tests/test_oracle_bb_pins.py): P^2 = P,
+E' M' E'^T = |Omega| I, the kernel relations of Sec. 3 and Sec. 4.4.2; the
+pseudo-Schur operator against a dense matrix assembled entry by entry from
+the definitions of Sec. 4.4.3 (from the raw mesh arrays, not these sparse
+operators); apply_bb_exact's outputs satisfying the pseudo-Schur system, the
+definition of y and the K+1 Laplacian equations in that dense form; with the
+exact Schur complement routed through apply_bb_exact itself, GMRES on
+J_P P^-1 converging in two steps and (J_P P^-1 - I)^2 vanishing on the range;
+planted mistakes (y with the other sign, P^T dropped, a sign slip inside the
+pseudo-Schur operator) each failing one of these pins; the commutator being
+small for a translation and large when B~ is misread; and projected solve +
+recovery agreeing with the grounded direct solve of J_s.
 """
 
 from __future__ import annotations
@@ -118,24 +125,55 @@ def _solve_laplacian_zero_sum(L, b):
     return x - x.mean()
 
 
-def apply_bb_exact(prob: Problem, phi, rho, s, c, d):
+def exact_schur_solve(prob: Problem, phi, rho, s, rhs):
+    """Least-squares solution w of P (C + B A^+ B^T) P^T w = rhs (dense).
+
+    The exact projected Schur complement of J_P is -P (C + B A^+ B^T) P^T
+    (Sec. 4.4.2).  TEST-ONLY and for tiny meshes: it forms the dense
+    pseudo-inverse of the K+1 Laplacians.  It stands in for the pseudo-Schur
+    step of the BB preconditioner, so that the rest of apply_bb_exact can be
+    checked against the ideal block-triangular preconditioner.
+    """
+    A, B, C = kkt_blocks(prob, phi, rho, s)
+    P = proj_matrix(prob).toarray()
+    Ap = np.linalg.pinv(A.toarray(), rcond=1e-12)
+    Bd = B.toarray()
+    Shat = P @ (C.toarray() + Bd @ Ap @ Bd.T) @ P.T
+    return np.linalg.lstsq(Shat, np.ravel(rhs), rcond=1e-12)[0].reshape(prob.K, prob.nc)
+
+
+def apply_bb_exact(prob: Problem, phi, rho, s, c, d, schur="bb", return_zeta=False):
     """(x; y) = P_BB^-1 (c; d) with exact inner solves.
 
     c: (K+1, nf), d: (K, nc).  Steps (Sec. 4.4.3):
-      z = S_BB^-1 (-Diag(rho) P d);  y = P^T M'^-1 A~ z;
+      z = S_BB^-1 (-Diag(rho) P d);  w = M'^-1 A~ z;  y = P^T w;
       b = c - B^T y;  x^k = (A^k)^+ (b^k - mean), zero-sum.
+    schur="exact" (test-only, tiny meshes) replaces the first two steps by
+    the exact projected Schur solve w = [P (C + B A^+ B^T) P^T]^+ (-P d),
+    which turns the whole application into the ideal block upper-triangular
+    preconditioner of Sec. 4.4.2.  return_zeta=True also returns z (None in
+    the exact mode).
     """
     o, K = prob.ops, prob.K
     _, B, _ = kkt_blocks(prob, phi, rho, s)
-    S = pseudo_schur(prob, phi, rho, s)
-    z = spla.spsolve(S.tocsc(), -(rho * proj(prob, d)).ravel())
-    At = coarse_laplacian_blocks(prob, rho)
-    y = proj_t(prob, ((At @ z).reshape(K, prob.nc)) / o.ac[None, :])
+    z = None
+    if schur == "bb":
+        S = pseudo_schur(prob, phi, rho, s)
+        z = spla.spsolve(S.tocsc(), -(rho * proj(prob, d)).ravel())
+        At = coarse_laplacian_blocks(prob, rho)
+        w = ((At @ z).reshape(K, prob.nc)) / o.ac[None, :]
+    elif schur == "exact":
+        w = exact_schur_solve(prob, phi, rho, s, -proj(prob, d))
+    else:
+        raise ValueError(f"unknown schur mode {schur}")
+    y = proj_t(prob, w)
     b = c.ravel() - B.T @ y.ravel()
     b = b.reshape(K + 1, prob.nf)
     from .ipm import edge_density
     rt = edge_density(prob, rho)
     x = np.stack([_solve_laplacian_zero_sum(o.laplacian(rt[k]), b[k]) for k in range(K + 1)])
+    if return_zeta:
+        return x, y, (None if z is None else z.reshape(K, prob.nc))
     return x, y
 
 
