@@ -57,6 +57,7 @@ extern "C" {
 #define OT_ENEWTON    -6   /* Newton iteration cap reached at some mu        */
 #define OT_EDEVICE    -7   /* HIP runtime error                              */
 #define OT_ENOMEM     -8   /* device or host allocation failed               */
+#define OT_ETIME      -9   /* ot_options.max_seconds reached in a solve      */
 
 #define OT_FP64   0        /* every kernel in FP64                           */
 #define OT_MIXED  1        /* preconditioner in FP32, the rest in FP64       */
@@ -130,6 +131,10 @@ typedef struct {
                                 below this value (counted as a failure)     */
     int32_t max_fgmres, restart, max_inner, max_newton, inner_restart;
     int32_t max_inner_S;     /* cap of the pseudo-Schur inner GMRES (see above) */
+    double max_seconds;      /* > 0: a solve (ot_solve, ot_state_solve) starts
+                                no further Newton step once this much wall
+                                time has passed and returns OT_ETIME with the
+                                last iterate kept; 0: no limit             */
     int32_t step_rule;       /* OT_STEP_COMMON (default): one step length for
                                 (phi, rho, s), the largest that keeps rho and
                                 s positive times frac_to_boundary (Sec. 2.4);
@@ -247,8 +252,30 @@ int  ot_apply_schur_prec(ot_state *st, const double *r, double *z);
  * Gradient of the transport cost at the current (converged) state with
  * respect to rho_in and rho_f (envelope term plus one adjoint saddle solve),
  * projected orthogonal to the coarse areas a'.  g_in, g_f: n_coarse each.
+ * The objective is the kinetic energy of Sec. 1 in the discrete form of
+ * Sec. 2.3; the adjoint system is the symmetric saddle system of Sec. 3.1,
+ * solved through the projected system of Sec. 4.4.2 with the BB
+ * preconditioner.  Every step runs on the device.  When the adjoint FGMRES
+ * solve misses eps_out it is repeated once with the FP64 preconditioner and
+ * inner tolerances / 10; if that also misses, the gradient is still written
+ * and OT_ELINSOLVE is returned.
+ * Errors: OT_EINVAL, OT_ELINSOLVE, OT_EDEVICE.
  */
 int  ot_gradient(ot_state *st, double *g_in, double *g_f);
+
+/*
+ * Interior-point continuation (Sec. 2.4) on an existing state, from its
+ * current iterate and mu (mu0 after ot_state_create; an imported iterate
+ * and mu resume a run): mu, mu * mu_factor, ... each solved by inexact
+ * Newton steps to |F_mu| <= tol (final_tol at the last one), ending after
+ * the first mu below tol or at or below opt.mu_stop.  The state keeps the
+ * last iterate, so ot_outputs, ot_state_export and ot_gradient can follow.
+ * tol <= 0 takes the state's option.  stats (may be NULL) receives the
+ * counts of this call and cost, dual and gap at its end.
+ * Errors: OT_EINVAL, OT_ELINSOLVE, OT_ENEWTON, OT_ETIME, OT_EDEVICE,
+ * OT_ENOMEM.
+ */
+int  ot_state_solve(ot_state *st, double tol, ot_stats *stats);
 
 /* Outputs at the current state: cost (kinetic energy), dual value D*, and
  * phi normalised so that sum_k a^T phi^k = 0 (phi_out may be NULL). */
@@ -272,12 +299,14 @@ const char *ot_last_error(void);
  * output pointer may be NULL.  OT_KPROF_NONE switches timing off.  Not for
  * concurrent use from several threads.
  *   CHEB_FINE     Chebyshev smoothing step of the K+1 Laplacians at the fine
- *                 multigrid level (Sec. 4.4.5 inner solves)
- *   SCHUR_BTILDE  pseudo-Schur operator, pass M^-1 B~ z (Sec. 4.4.4)
+ *                 multigrid level (the Laplacian solves of the BB
+ *                 preconditioner, Sec. 4.4.3)
+ *   SCHUR_BTILDE  pseudo-Schur operator, pass M^-1 B~ z (B~ of Sec. 4.4.3)
  *   SCHUR_OUT     pseudo-Schur operator, pass Diag(s) A~ z - Diag(rho) B v
+ *                 (Sec. 4.4.3)
  *   TRI_FINE      time-line tridiagonal solve on the density cells
  *   MULTIDOT      dot products of one vector with a Krylov basis (Arnoldi)
- *   SADDLE_PHI    potential block of the saddle operator J_P (Sec. 4.1)
+ *   SADDLE_PHI    potential block of the saddle operator J_P (Sec. 4.4.2)
  */
 enum {
     OT_KPROF_NONE = 0, OT_KPROF_CHEB_FINE = 1, OT_KPROF_SCHUR_BTILDE = 2, OT_KPROF_SCHUR_OUT = 3,

@@ -12,8 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG, OT_ELINSOLVE, OT_ENEWTON,  # noqa: F401
-                   OT_EDEVICE, OT_ENOMEM, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OTError, Options, Stats,
-                   check, lib)
+                   OT_EDEVICE, OT_ENOMEM, OT_ETIME, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OTError, Options,
+                   Stats, check, lib)
 
 __all__ = ["Mesh", "State", "solve", "solve_batched", "options", "OTCost", "OTError", "Stats",
            "kprof_select", "kprof_read", "KPROF"]
@@ -220,11 +220,22 @@ class State:
         check(lib().ot_outputs(self._h, C.byref(cost), C.byref(dual), p))
         return cost.value, dual.value, phi
 
-    def gradient(self):
+    def solve(self, tol=0.0, raise_on_error=True):
+        """Interior-point continuation from the current iterate and mu
+        (ot_state_solve); returns (rc, stats)."""
+        st = Stats()
+        rc = lib().ot_state_solve(self._h, float(tol), C.byref(st))
+        if raise_on_error and rc != OT_OK:
+            check(rc)
+        return rc, st
+
+    def gradient(self, raise_on_error=True):
         nc = self.mesh.n_coarse
         gi, p1 = self._out(nc)
         gf, p2 = self._out(nc)
-        check(lib().ot_gradient(self._h, p1, p2))
+        rc = lib().ot_gradient(self._h, p1, p2)
+        if raise_on_error and rc != OT_OK:
+            check(rc)
         return gi, gf
 
     def __del__(self):
@@ -304,10 +315,8 @@ def _make_otcost():
             dev = rho_in.is_cuda
             st = State(mesh, rho_in.detach().double().contiguous(), rho_f.detach().double().contiguous(), K,
                        device=dev, **opts)
-            rc = _run_ipm(st, tol)
-            if rc != OT_OK:
-                check(rc)
-            cost, _, _ = st.outputs()
+            _, stats = st.solve(tol)
+            cost = stats.cost
             ctx.state = st
             return torch.tensor(cost, dtype=torch.float64, device=rho_in.device)
 
@@ -321,36 +330,6 @@ def _make_otcost():
             return gi, gf, None, None, None
 
     return OTCost
-
-
-def _run_ipm(st, tol, mu_factor=None):
-    """Continuation loop over mu through ot_newton_step (same schedule as
-    ot_solve); keeps the state for the backward pass."""
-    o = st.opt
-    mu = o.mu0
-    st.set_mu(mu)
-    fac = o.mu_factor if mu_factor is None else mu_factor
-    for _ in range(400):
-        last = mu < tol or (o.mu_stop > 0 and mu <= o.mu_stop * (1 + 1e-12))
-        tl = o.final_tol if (last and o.final_tol > 0) else tol
-        ok = False
-        for it in range(o.max_newton + 1):
-            _, nrm = st.residual()
-            if nrm <= tl:
-                ok = True
-                break
-            if it == o.max_newton:
-                break
-            rc, stats, _ = st.newton_step(raise_on_error=False)
-            if rc != OT_OK and not (rc == OT_ELINSOLVE and stats.last_relres <= o.accept_relres):
-                return rc
-        if not ok:
-            return OT_ENEWTON
-        if last:
-            return OT_OK
-        mu *= fac
-        st.set_mu(mu)
-    return OT_ENEWTON
 
 
 class _LazyOTCost:

@@ -11,14 +11,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libotbb.so")
 
 OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG = 0, -1, -2, -3, -4
-OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM = -5, -6, -7, -8
+OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM, OT_ETIME = -5, -6, -7, -8, -9
 OT_FP64, OT_MIXED = 0, 1
 OT_HOST, OT_DEVICE = 0, 1
 
 ERROR_NAMES = {
     OT_EINVAL: "OT_EINVAL", OT_EMESH: "OT_EMESH", OT_EMASS: "OT_EMASS", OT_ENEG: "OT_ENEG",
     OT_ELINSOLVE: "OT_ELINSOLVE", OT_ENEWTON: "OT_ENEWTON", OT_EDEVICE: "OT_EDEVICE",
-    OT_ENOMEM: "OT_ENOMEM",
+    OT_ENOMEM: "OT_ENOMEM", OT_ETIME: "OT_ETIME",
 }
 
 dptr = C.POINTER(C.c_double)
@@ -32,7 +32,7 @@ class Options(C.Structure):
         ("final_tol", C.c_double), ("mu_stop", C.c_double), ("accept_relres", C.c_double),
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
         ("max_newton", C.c_int32), ("inner_restart", C.c_int32), ("max_inner_S", C.c_int32),
-        ("step_rule", C.c_int32),
+        ("max_seconds", C.c_double), ("step_rule", C.c_int32),
         ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p),
     ]
@@ -91,6 +91,7 @@ SIGNATURES = {
     "ot_apply_saddle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_apply_schur_prec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ot_state_solve": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(Stats)]),
     "ot_outputs": (C.c_int, [C.c_void_p, dptr, dptr, C.c_void_p]),
     "ot_last_error": (C.c_char_p, []),
     "ot_kprof_select": (C.c_int, [C.c_int32, C.c_int32]),

@@ -1187,5 +1187,64 @@ __global__ void k_adjoint_corr(MeshView m, const double *__restrict__ ph, const 
     out[j] = v + 0.5 * gg;
 }
 
+// Adjoint right-hand side of the cost gradient: the rho block of the Newton
+// system gets dt a' s (phi block zero, set by the caller); gt holds the same
+// values for the recovery.  Partial sums of squares for its norm.
+__global__ void k_grad_rhs(int nc, const double *__restrict__ ac, StateView S, double *__restrict__ gt,
+                           double *__restrict__ out_rho, double *__restrict__ part) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    double sq = 0.0;
+    if (j < nc) {
+        const size_t q = (size_t)k * nc + j;
+        const double v = S.dt * ac[j] * S.s[q];
+        gt[q] = v;
+        out_rho[q] = v;
+        sq = v * v;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sq;
+}
+
+// Gradient assembly per coarse cell from the envelope parts (Omega^T phi and
+// R_T (grad phi)^2 at the first / last potential level) and the adjoint
+// corrections:
+//   g_in = -Omega^T phi^1 - dt/4 R_T (grad phi^1)^2 - corr_first
+//   g_f  =  Omega^T phi^{K+1} - dt/4 R_T (grad phi^{K+1})^2 - corr_last
+// b holds [corr_first, corr_last, om_first, om_last, rt_first, rt_last],
+// nc each.  Partial sums of a' g_in, a' g_f and a' a' per block
+// (part[0 / 1 / 2 * nblk + b]) for the projection orthogonal to a'.
+__global__ void k_grad_assemble(int nc, const double *__restrict__ ac, double dt, const double *__restrict__ b,
+                                double *__restrict__ gi, double *__restrict__ gf, double *__restrict__ part) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    double si = 0.0, sf = 0.0, sa = 0.0;
+    if (j < nc) {
+        const double vi = -b[2 * (size_t)nc + j] - 0.25 * dt * b[4 * (size_t)nc + j] - b[j];
+        const double vf = b[3 * (size_t)nc + j] - 0.25 * dt * b[5 * (size_t)nc + j] - b[(size_t)nc + j];
+        gi[j] = vi;
+        gf[j] = vf;
+        si = ac[j] * vi;
+        sf = ac[j] * vf;
+        sa = ac[j] * ac[j];
+    }
+    si = block_sum(si);
+    sf = block_sum(sf);
+    sa = block_sum(sa);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = si;
+        part[gridDim.x + blockIdx.x] = sf;
+        part[2 * gridDim.x + blockIdx.x] = sa;
+    }
+}
+
+// g -= a' (a'^T g) / (a'^T a') for both gradients; sums = [a'g_in, a'g_f, a'a']
+__global__ void k_grad_project(int nc, const double *__restrict__ ac, const double *__restrict__ sums,
+                               double *__restrict__ gi, double *__restrict__ gf) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= nc) return;
+    const double aa = sums[2];
+    gi[j] -= ac[j] * sums[0] / aa;
+    gf[j] -= ac[j] * sums[1] / aa;
+}
+
 }  // namespace kern
 }  // namespace otbb

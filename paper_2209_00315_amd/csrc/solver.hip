@@ -965,6 +965,32 @@ static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
     return its;
 }
 
+// Solve the Newton system held in rhs / gt, and when FGMRES ends above
+// accept_relres, once more with the FP64 preconditioner, inner tolerances
+// / 10 and the pseudo-Schur cap lifted to the general inner cap (the
+// failure policy for the linear solves; the paper reports such failures
+// and stops).  strict: retry whenever eps_out was missed.  The right-hand
+// side is untouched by a solve, so the retry starts from the same system.
+static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = false) {
+    solve_newton_system(st, rhs_norm_abs);
+    if (st->last_converged || (!strict && st->last_relres <= st->opt.accept_relres)) return;
+    const ot_options saved = st->opt;
+    const int its1 = st->last_iters;
+    const double rr1 = st->last_relres;
+    st->opt.precision = OT_FP64;
+    st->opt.eps_in_S = 0.1 * saved.eps_in_S;
+    st->opt.eps_in_A = 0.1 * saved.eps_in_A;
+    st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
+    linearize(st);
+    solve_newton_system(st, rhs_norm_abs);
+    st->acc.linear_systems--;              // one Newton system, two attempts
+    if (st->opt.verbose)
+        fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1, st->last_iters,
+                st->last_relres);
+    st->opt = saved;
+    st->lin_valid = false;
+}
+
 static void renormalize(ot_state *st) {
     const ot_mesh *m = st->mesh;
     double *mass = st->sums.p;
@@ -992,27 +1018,7 @@ static int newton_step(ot_state *st, double *res_before) {
     linearize(st);
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
-    solve_newton_system(st, fn);
-    if (!st->last_converged && !(st->last_relres <= st->opt.accept_relres)) {
-        // a step that would be rejected: retry once with the FP64
-        // preconditioner, inner tolerances / 10 and the pseudo-Schur cap
-        // lifted to the general inner cap
-        const ot_options saved = st->opt;
-        const int its1 = st->last_iters;
-        const double rr1 = st->last_relres;
-        st->opt.precision = OT_FP64;
-        st->opt.eps_in_S = 0.1 * saved.eps_in_S;
-        st->opt.eps_in_A = 0.1 * saved.eps_in_A;
-        st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
-        linearize(st);
-        solve_newton_system(st, fn);
-        st->acc.linear_systems--;              // one Newton system, two attempts
-        if (st->opt.verbose)
-            fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1,
-                    st->last_iters, st->last_relres);
-        st->opt = saved;
-        st->lin_valid = false;
-    }
+    solve_with_retry(st, fn);
     int rc = OT_OK;
     if (!st->last_converged) {
         st->acc.failures++;
@@ -1136,6 +1142,7 @@ void check_options(const ot_options &o) {
     OT_REQUIRE(o.mu0 > 0 && o.mu_factor > 0 && o.mu_factor < 1, OT_EINVAL, "bad mu schedule");
     OT_REQUIRE(o.frac_to_boundary > 0 && o.frac_to_boundary < 1, OT_EINVAL, "bad step fraction");
     OT_REQUIRE(o.accept_relres >= 0 && o.accept_relres < 1, OT_EINVAL, "bad accept_relres");
+    OT_REQUIRE(o.max_seconds >= 0.0, OT_EINVAL, "max_seconds must be >= 0");
     OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart < kMaxBasis && o.max_inner >= 1 && o.max_inner_S >= 1 &&
                    (o.step_rule == OT_STEP_COMMON || o.step_rule == OT_STEP_SPLIT) && o.mu_stop >= 0.0 &&
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
@@ -1194,7 +1201,7 @@ ot_state *create_state(const ot_mesh *m, const double *rho_in, const double *rho
     st->rin.upload(ri, s); st->rf.upload(rf, s);
     st->F.alloc(st->nphi + 2 * st->mrho);
     st->rhs.alloc(st->N); st->sol.alloc(st->N); st->gt.alloc(st->mrho);
-    st->tmpN.alloc(std::max(st->N, (size_t)6 * nc)); st->tmpr.alloc(st->mrho); st->ds.alloc(st->mrho);
+    st->tmpN.alloc(std::max(st->N, (size_t)8 * nc)); st->tmpr.alloc(st->mrho); st->ds.alloc(st->mrho);
     st->sums.alloc(8 * (K + 2) + 256);
     st->shift.alloc(std::max(K + 2, kMaxBasis + 1));
     size_t np = (size_t)(ceil_div(std::max(std::max(nf, nc), std::max(m->h.ne, 1)), BS) + 1) * (2 * K + 4) +
@@ -1208,12 +1215,13 @@ ot_state *create_state(const ot_mesh *m, const double *rho_in, const double *rho
     return st.release();
 }
 
-// continuation driver (Sec. 2.4); returns OT code
+// continuation driver (Sec. 2.4) from the state's current iterate and mu:
+// mu, mu f, mu f^2, ... each solved to |F_mu| <= tol by Newton steps, ending
+// after the first mu below tol (or at or below mu_stop); returns OT code
 int run_ipm(ot_state *st, double tol) {
     const ot_options &o = st->opt;
     double t0 = now_s();
     int rc = OT_OK;
-    st->mu = o.mu0;
     for (int l = 0; l < 400; ++l) {
         const bool last = st->mu < tol || (o.mu_stop > 0.0 && st->mu <= o.mu_stop * (1.0 + 1e-12));
         const double tl = (last && o.final_tol > 0) ? o.final_tol : tol;
@@ -1223,6 +1231,7 @@ int run_ipm(ot_state *st, double tol) {
             st->acc.final_residual = fn;
             if (fn <= tl) { ok = true; break; }
             if (it == o.max_newton) break;
+            if (o.max_seconds > 0.0 && now_s() - t0 > o.max_seconds) { rc = OT_ETIME; break; }
             int r = newton_step(st, nullptr);
             if (r != OT_OK && !(st->last_relres <= o.accept_relres)) { rc = r; break; }
         }
@@ -1249,6 +1258,7 @@ void ot_options_default(ot_options *o) {
     o->accept_relres = 1e-2;
     o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 60; o->inner_restart = 30;
     o->max_inner_S = 10;
+    o->max_seconds = 0.0;
     o->step_rule = OT_STEP_COMMON;
     o->precision = OT_MIXED; o->mem_kind = OT_HOST; o->verbose = 0; o->stream = nullptr;
 }
@@ -1502,6 +1512,38 @@ int ot_solve(const ot_mesh *m, const double *rho_in, const double *rho_f, int32_
         if (stats) *stats = st->acc;
         if (rc == OT_ELINSOLVE) set_last_error("FGMRES failed");
         if (rc == OT_ENEWTON) set_last_error("Newton iteration cap reached");
+        if (rc == OT_ETIME) set_last_error("time limit max_seconds reached");
+    });
+    return g != OT_OK ? g : rc;
+}
+
+int ot_state_solve(ot_state *st, double tol, ot_stats *stats) {
+    int rc = OT_OK;
+    int g = guard([&] {
+        OT_REQUIRE(st, OT_EINVAL, "null state");
+        const double t = tol > 0 ? tol : st->opt.tol;
+        const ot_stats before = st->acc;
+        rc = run_ipm(st, t);
+        double cost = 0, dual = 0;
+        outputs(st, &cost, &dual);
+        st->acc.cost = cost; st->acc.dual = dual; st->acc.gap = cost - dual;
+        if (stats) {
+            *stats = st->acc;
+            stats->ip_steps -= before.ip_steps;
+            stats->newton_steps -= before.newton_steps;
+            stats->linear_systems -= before.linear_systems;
+            stats->outer_iters -= before.outer_iters;
+            stats->inner_S_iters -= before.inner_S_iters;
+            stats->inner_A_iters -= before.inner_A_iters;
+            stats->prec_applies -= before.prec_applies;
+            stats->failures -= before.failures;
+            stats->seconds_total -= before.seconds_total;
+            stats->seconds_linear -= before.seconds_linear;
+            stats->seconds_setup -= before.seconds_setup;
+        }
+        if (rc == OT_ELINSOLVE) set_last_error("FGMRES failed");
+        if (rc == OT_ENEWTON) set_last_error("Newton iteration cap reached");
+        if (rc == OT_ETIME) set_last_error("time limit max_seconds reached");
     });
     return g != OT_OK ? g : rc;
 }
@@ -1522,60 +1564,45 @@ int ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes, const double *
 }
 
 int ot_gradient(ot_state *st, double *g_in, double *g_f) {
-    return guard([&] {
+    int rc = OT_OK;
+    int g = guard([&] {
         OT_REQUIRE(st && g_in && g_f, OT_EINVAL, "null argument");
         const ot_mesh *m = st->mesh;
         hipStream_t s = st->stream;
         const int K = st->K, nf = m->h.nf, nc = m->h.nc;
         MeshView mv = mesh_view(m);
         StateView sv = st->view();
-        // adjoint right-hand side (0; dt a' s), projected system + recovery
+        // adjoint right-hand side (0; dt a' s): projected system + recovery
         k_fill<double><<<grid1(st->nphi), BS, 0, s>>>(st->rhs, st->nphi, 0.0);
-        std::vector<double> ac(m->h.ac);
-        std::vector<double> sh(st->mrho);
-        OT_HIP(hipMemcpyAsync(sh.data(), st->s.p, st->mrho * sizeof(double), hipMemcpyDeviceToHost, s));
-        OT_HIP(hipStreamSynchronize(s));
-        double nrm = 0.0;
-        for (int k = 0; k < K; ++k)
-            for (int j = 0; j < nc; ++j) {
-                double v = st->dt * ac[j] * sh[(size_t)k * nc + j];
-                sh[(size_t)k * nc + j] = v;
-                nrm += v * v;
-            }
-        OT_HIP(hipMemcpyAsync(st->gt.p, sh.data(), st->mrho * sizeof(double), hipMemcpyHostToDevice, s));
-        OT_HIP(hipMemcpyAsync(st->rhs.p + st->nphi, sh.data(), st->mrho * sizeof(double), hipMemcpyHostToDevice, s));
+        dim3 gc = grid2(nc, K);
+        k_grad_rhs<<<gc, BS, 0, s>>>(nc, m->ac, sv, st->gt, st->rhs.p + st->nphi, st->red.part);
+        const double nrm = std::sqrt(st->red.fetch(st->red.seg_final(1, gc.x * gc.y), 1)[0]);
         st->lin_valid = false;
         linearize(st);
-        solve_newton_system(st, std::sqrt(nrm));
-        // corrections and envelope terms
-        double *b = st->tmpN.p;
+        solve_with_retry(st, nrm, true);
+        if (!st->last_converged) {
+            st->acc.failures++;
+            rc = OT_ELINSOLVE;
+        }
+        // corrections, envelope terms, assembly and projection, on the device
+        double *b = st->tmpN.p, *gi = b + 6 * (size_t)nc, *gf = b + 7 * (size_t)nc;
         const double *q1 = st->sol.p, *qK = st->sol.p + (size_t)K * nf;
         const double *p1 = st->phi.p, *pK = st->phi.p + (size_t)K * nf;
         k_adjoint_corr<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, p1, q1, 1.0, st->dt, b);
         k_adjoint_corr<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, pK, qK, -1.0, st->dt, b + nc);
         k_boundary_terms<<<grid1(nc, 1 << 20), BS, 0, s>>>(mv, sv, p1, pK, b + 2 * nc, b + 3 * nc, b + 4 * nc,
                                                           b + 5 * nc);
-        std::vector<double> h(6 * (size_t)nc);
-        OT_HIP(hipMemcpyAsync(h.data(), b, 6 * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        const int nblk = ceil_div(nc, BS);
+        k_grad_assemble<<<nblk, BS, 0, s>>>(nc, m->ac, st->dt, b, gi, gf, st->red.part);
+        k_seg_final<<<3, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
+        k_grad_project<<<nblk, BS, 0, s>>>(nc, m->ac, st->red.dev, gi, gf);
+        copy_out(g_in, gi, nc, st->opt.mem_kind, s);
+        copy_out(g_f, gf, nc, st->opt.mem_kind, s);
         OT_HIP(hipStreamSynchronize(s));
-        std::vector<double> gi(nc), gf(nc);
-        for (int j = 0; j < nc; ++j) {
-            gi[j] = -h[2 * nc + j] - 0.25 * st->dt * h[4 * nc + j] - h[j];
-            gf[j] = h[3 * nc + j] - 0.25 * st->dt * h[5 * nc + j] - h[nc + j];
-        }
-        double aa = 0, ai = 0, af = 0;
-        for (int j = 0; j < nc; ++j) { aa += ac[j] * ac[j]; ai += ac[j] * gi[j]; af += ac[j] * gf[j]; }
-        for (int j = 0; j < nc; ++j) { gi[j] -= ac[j] * ai / aa; gf[j] -= ac[j] * af / aa; }
-        if (st->opt.mem_kind == OT_DEVICE) {
-            OT_HIP(hipMemcpyAsync(g_in, gi.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
-            OT_HIP(hipMemcpyAsync(g_f, gf.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
-            OT_HIP(hipStreamSynchronize(s));
-        } else {
-            std::memcpy(g_in, gi.data(), nc * sizeof(double));
-            std::memcpy(g_f, gf.data(), nc * sizeof(double));
-        }
         st->lin_valid = false;
+        if (rc != OT_OK) set_last_error("adjoint FGMRES solve did not reach eps_out (FP64 retry included)");
     });
+    return g != OT_OK ? g : rc;
 }
 
 }  // extern "C"

@@ -29,8 +29,7 @@ def test_first_mu_at_full_size():
     dev = torch.device("cuda")
     st = ot.State(mesh, torch.as_tensor(ri, device=dev), torch.as_tensor(rf, device=dev), K, device=True,
                   precision="mixed", mu_stop=1.0)
-    from paper_2209_00315_amd import _run_ipm
-    rc = _run_ipm(st, 1e-6)
+    rc, _ = st.solve(1e-6)
     assert rc == ot.OT_OK
     F_gpu, nrm = st.residual()
     phi, rho, s, mu = st.export()
