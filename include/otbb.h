@@ -64,6 +64,9 @@ extern "C" {
 #define OT_STEP_COMMON 0   /* step rules, see ot_options.step_rule           */
 #define OT_STEP_SPLIT  1
 
+#define OT_PREC_BB     0   /* BB block-triangular preconditioner (Sec. 4.4.3) */
+#define OT_PREC_SIMPLE 1   /* SIMPLE preconditioner (Sec. 4.3), FP64       */
+
 #define OT_HOST   0
 #define OT_DEVICE 1
 
@@ -131,10 +134,32 @@ typedef struct {
                                 below this value (counted as a failure)     */
     int32_t max_fgmres, restart, max_inner, max_newton, inner_restart;
     int32_t max_inner_S;     /* cap of the pseudo-Schur inner GMRES (see above) */
+    double eps_out_min;      /* tightest FGMRES tolerance of a Newton step
+                                (relative, like eps_out; default 1e-10).
+                                Once FGMRES meets eps_out, the step length
+                                of its direction is checked; below 0.9 (and
+                                still growing by 10% per check) the
+                                tolerance is divided by 100, down to this
+                                value, and FGMRES continues in the same
+                                Krylov space.  eps_out_min >= eps_out
+                                switches the rule off.                      */
     double max_seconds;      /* > 0: a solve (ot_solve, ot_state_solve) starts
                                 no further Newton step once this much wall
                                 time has passed and returns OT_ETIME with the
                                 last iterate kept; 0: no limit             */
+    double neighborhood;     /* gamma in [0, 1): > 0 shortens the common step
+                                further so that every cell keeps
+                                rho s >= gamma mu (a neighbourhood of the
+                                central path, keeping the next Newton system
+                                well scaled); 0 (default): positivity only */
+    int32_t preconditioner;  /* OT_PREC_BB (default) or OT_PREC_SIMPLE: the
+                                SIMPLE preconditioner of Sec. 4.3 on the
+                                projected system, u = Diag(A)^-1 c,
+                                P (C + B Diag(A)^-1 B^T) P^T y = P B u - d
+                                by PCG to eps_in_S (cap max_inner) with its
+                                exact time-line tridiagonal part as
+                                preconditioner, x = u - Diag(A)^-1 B^T P^T y;
+                                always FP64 (precision applies to BB)      */
     int32_t step_rule;       /* OT_STEP_COMMON (default): one step length for
                                 (phi, rho, s), the largest that keeps rho and
                                 s positive times frac_to_boundary (Sec. 2.4);
@@ -154,6 +179,7 @@ typedef struct {
     double final_residual, mu;
     double cost, dual, gap;
     double last_relres;      /* FGMRES relative residual of the last system  */
+    int32_t tightenings;     /* FGMRES tolerance tightenings (eps_out_min)   */
 } ot_stats;
 
 void ot_options_default(ot_options *opt);
@@ -167,6 +193,12 @@ int  ot_mesh_create(const ot_mesh_desc *desc, ot_mesh **out);
  * diagonal.  cartesian = 1 instead gives the single n x n Cartesian grid
  * (J = identity).  Errors: OT_EINVAL. */
 int  ot_mesh_create_structured(int32_t n, int32_t cartesian, ot_mesh **out);
+/* The n x n x n grid of cubes on [0,1]^3 for both levels (J = identity),
+ * the three-dimensional workload of Sec. 4.1: cell (c n + b) n + a, the
+ * interior faces as TPFA edges (|e| = h^2, d_e = h, lambda_e = 1/2), cell
+ * volumes h^3 as areas; the coarse edges of the BB coarse Laplacian are
+ * the same faces.  Errors: OT_EINVAL (n outside [2, 1024]). */
+int  ot_mesh_create_cartesian3d(int32_t n, ot_mesh **out);
 void ot_mesh_destroy(ot_mesh *mesh);
 int  ot_mesh_sizes(const ot_mesh *mesh, int32_t *n_fine, int32_t *n_coarse,
                    int32_t *n_fedge, int32_t *n_cedge);
@@ -286,6 +318,11 @@ int  ot_state_set_options(ot_state *st, const ot_options *opt);
 
 /* Message of the last error on this thread (never NULL). */
 const char *ot_last_error(void);
+
+/* sizeof(ot_options), sizeof(ot_stats) and sizeof(ot_mesh_desc) as this
+ * library was built (any pointer may be NULL): a binding checks them
+ * against its own declarations before it passes any of these structs. */
+void ot_abi_sizes(int32_t *options_bytes, int32_t *stats_bytes, int32_t *mesh_desc_bytes);
 
 /*
  * Kernel timing (instrumentation of the hot path, process-wide).

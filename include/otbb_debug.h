@@ -17,7 +17,8 @@ extern "C" {
 
 /* out = {n_fine, n_coarse, n_fedge, n_cedge, n_overlap, multigrid levels,
  *        coarse-cell colors, fine-cell ELL width} of the structured mesh of
- * ot_mesh_create_structured(n, cartesian).  Errors: OT_EINVAL. */
+ * ot_mesh_create_structured(n, cartesian), or of ot_mesh_create_cartesian3d(n)
+ * when cartesian == 3.  Errors: OT_EINVAL. */
 int otbb_debug_structured_sizes(int32_t n, int32_t cartesian, int32_t out[8]);
 
 /* Copy the arrays of that mesh into caller buffers sized from

@@ -199,14 +199,33 @@ def step_length(x, dx, tau=0.99):
     return min(1.0, tau * amax)
 
 
-def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common"):
+def central_step(rho, s, drho, ds, gmu, amax):
+    """Largest step t <= amax with (rho + t drho)(s + t ds) >= gmu in every
+    cell where rho s > gmu holds at t = 0: per cell the first positive root
+    of the quadratic a t^2 + b t + c, a = drho ds, b = rho ds + s drho,
+    c = rho s - gmu (np.roots per cell, plain and slow)."""
+    t = amax
+    for r, sv, dr, d in zip(rho.ravel(), s.ravel(), drho.ravel(), ds.ravel()):
+        c = r * sv - gmu
+        if c <= 0:
+            continue
+        roots = np.roots([dr * d, r * d + sv * dr, c])
+        pos = [x.real for x in roots if abs(x.imag) == 0.0 and x.real > 0]
+        if pos:
+            t = min(t, min(pos))
+    return t
+
+
+def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common", neighborhood=0.0):
     """One Newton update of (phi, rho, s) at fixed mu with a direct solve.
 
     step_rule "common" (the reading of the positivity line search of Sec. 2.4):
     one step length for all three blocks, tau times the largest that keeps rho
     and s positive.  "split": phi and rho take tau times the largest step that
     keeps rho positive, s the one that keeps s positive (a primal / dual split
-    of that line search)."""
+    of that line search).  neighborhood = gamma > 0 (common rule only)
+    shortens the step further so that rho s >= gamma mu holds in every cell
+    that satisfied it before (a neighbourhood of the central path)."""
     K, nf, nc = prob.K, prob.nf, prob.nc
     f, g, h, gt = newton_rhs(prob, phi, rho, s, mu)
     J = saddle_matrix(prob, phi, rho, s)
@@ -220,6 +239,8 @@ def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common"):
         return phi + a_p * dphi, rho + a_p * drho, s + a_d * ds, alpha
     if step_rule != "common":
         raise ValueError(f"unknown step rule {step_rule}")
+    if neighborhood > 0:
+        alpha = central_step(rho, s, drho, ds, neighborhood * mu, alpha)
     return phi + alpha * dphi, rho + alpha * drho, s + alpha * ds, alpha
 
 
@@ -249,7 +270,7 @@ def initial_point(prob: Problem, mu0=1.0):
 
 def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
               max_newton=20, final_tol=None, start=None, mu_start=None,
-              max_mu_steps=200, mu_target=None, step_rule="common"):
+              max_mu_steps=200, mu_target=None, step_rule="common", neighborhood=0.0):
     """IP continuation: for mu_l = mu0 mu_factor^l, Newton until |F_mu| <= tol,
     warm-started from the previous mu; stop after the first mu < tol.
 
@@ -285,7 +306,7 @@ def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
                 break
             if it == max_newton:
                 break
-            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau, step_rule)
+            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau, step_rule, neighborhood)
             rho = renormalize(prob, rho, m0)
             count += 1
         newton_counts.append(count)

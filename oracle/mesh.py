@@ -36,7 +36,8 @@ stays defined.  This only affects the preconditioner, never the solution.
 Cartesian meshes
 ----------------
 The paper's Cartesian special case: both levels are the same n x n grid of
-squares, J is the identity.
+squares, J is the identity.  The three-dimensional workload (Sec. 4.1) uses
+the n x n x n grid of cubes in the same way, with faces as edges.
 
 Pins (tests/test_oracle_mesh.py): area sums, overlap row/column sums, edge
 counts, orientation of the density sides against direct geometric tests.
@@ -219,6 +220,38 @@ def cartesian_mesh(n: int) -> Mesh:
         ce_i=K.copy(), ce_j=L.copy(), ce_len=np.full(ne, h), ce_dist=np.full(ne, h),
         ce_lam=np.full(ne, 0.5),
         name=f"cartesian{n}",
+    )
+
+
+def cartesian3d_mesh(n: int) -> Mesh:
+    """n x n x n grid of cubes on [0,1]^3 for both levels (J = identity): the
+    three-dimensional workload of Sec. 4.1 (fourth test case).
+
+    Cell i = (c n + b) n + a is the cube [a h, (a+1) h] x [b h, (b+1) h] x
+    [c h, (c+1) h], h = 1/n.  The TPFA "edges" of Sec. 2.1 are the interior
+    faces: |e| = h^2 (face area), d_e = h (distance of the cell centres),
+    lambda_e = 1/2; K is the cell with the smaller coordinate along the
+    face normal.  "Areas" are cell volumes h^3.  The coarse edges of the BB
+    coarse Laplacian are the same faces.
+    """
+    if n < 2:
+        raise ValueError("n must be >= 2")
+    h = 1.0 / n
+    N = n ** 3
+    idx = np.arange(N, dtype=np.int64).reshape(n, n, n)     # [c, b, a]
+    K = np.concatenate([idx[:, :, :-1].ravel(), idx[:, :-1, :].ravel(), idx[:-1, :, :].ravel()])
+    L = np.concatenate([idx[:, :, 1:].ravel(), idx[:, 1:, :].ravel(), idx[1:, :, :].ravel()])
+    ne = K.size
+    return Mesh(
+        n_fine=N, n_coarse=N,
+        fine_area=np.full(N, h ** 3), coarse_area=np.full(N, h ** 3),
+        ov_fine=np.arange(N, dtype=np.int64), ov_coarse=np.arange(N, dtype=np.int64),
+        ov_area=np.full(N, h ** 3),
+        fe_K=K, fe_L=L, fe_rK=K.copy(), fe_rL=L.copy(),
+        fe_len=np.full(ne, h * h), fe_dist=np.full(ne, h), fe_lam=np.full(ne, 0.5),
+        ce_i=K.copy(), ce_j=L.copy(), ce_len=np.full(ne, h * h), ce_dist=np.full(ne, h),
+        ce_lam=np.full(ne, 0.5),
+        name=f"cartesian3d_{n}",
     )
 
 

@@ -12,7 +12,10 @@ Workloads (all on the unit square, marginals on the coarse/density cells):
     the benchmark configuration);
   * mixtures: k Gaussians with centres U[0.2, 0.8]^2, sigma U[0.05, 0.15],
     weights Dirichlet(1, ..., 1), optional uniform background;
-  * translation: sigma = 0.05 Gaussian moved from (0.35, 0.5) to (0.65, 0.5).
+  * translation: sigma = 0.05 Gaussian moved from (0.35, 0.5) to (0.65, 0.5);
+  * three dimensions: Gaussians of variance 0.1 at (0.3, 0.3, 0.3) and
+    (0.7, 0.7, 0.7) on the n^3 grid of cubes of [0,1]^3 (cube averages by the
+    4^3 midpoint rule).
 Cell averages: every coarse triangle is cut into 64 congruent sub-triangles
 (8 per edge), density sampled at their centroids; Cartesian squares use the
 8 x 8 midpoint rule.  Then floor at 1e-8 and scale to unit mass a'^T rho = 1.
@@ -109,6 +112,21 @@ def random_mixture(rng, k, background=0.0):
     return mixture(centres, sigmas, weights, background)
 
 
+def cube_averages(fn, n: int, m: int = 4) -> np.ndarray:
+    """Averages of fn(x, y, z) over the n^3 cubes of [0,1]^3 (cell
+    (c n + b) n + a), m^3-point midpoint rule per cube."""
+    h = 1.0 / n
+    t = (np.arange(m) + 0.5) / m
+    centres = (np.arange(n) * h)[:, None] + h * t[None, :]          # (n, m)
+    xs = centres.ravel()
+    X = xs[None, None, :]
+    Y = xs[None, :, None]
+    Z = xs[:, None, None]
+    vals = fn(X, Y, Z)                                                # [z, y, x] samples
+    vals = vals.reshape(n, m, n, m, n, m).mean(axis=(1, 3, 5))
+    return vals.ravel()
+
+
 def floor_normalize(vals, areas, floor=FLOOR):
     v = np.maximum(vals, floor)
     return v / float(areas @ v)
@@ -134,6 +152,24 @@ def translation_pair(n, mesh="structured", sigma=0.05, shift=0.3):
     mk = structured_marginal if mesh == "structured" else cartesian_marginal
     x0 = 0.5 - shift / 2
     return (mk(gaussian(x0, 0.5, sigma), n), mk(gaussian(x0 + shift, 0.5, sigma), n))
+
+
+def gaussian3d(cx, cy, cz, sigma):
+    c = 1.0 / ((2.0 * np.pi) ** 1.5 * sigma ** 3)
+
+    def f(x, y, z):
+        return c * np.exp(-((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (2.0 * sigma * sigma))
+    return f
+
+
+def gaussian3d_pair(n, sigma=np.sqrt(0.1), centres=((0.3, 0.3, 0.3), (0.7, 0.7, 0.7))):
+    """The three-dimensional workload on the n^3 cube grid: isotropic
+    Gaussians of variance 0.1 at (0.3, 0.3, 0.3) and (0.7, 0.7, 0.7) (the
+    paper's fourth test case; no benchmark configuration overrides the
+    variance here), cube averages by the 4^3 midpoint rule, floored and
+    normalised to unit mass; seed-free."""
+    vol = np.full(n ** 3, 1.0 / n ** 3)
+    return tuple(floor_normalize(cube_averages(gaussian3d(*c, sigma), n), vol) for c in centres)
 
 
 def mixture_pair(n, k, config, problem=0, background=0.0, mesh="structured"):

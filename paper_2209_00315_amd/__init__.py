@@ -12,8 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG, OT_ELINSOLVE, OT_ENEWTON,  # noqa: F401
-                   OT_EDEVICE, OT_ENOMEM, OT_ETIME, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OTError, Options,
-                   Stats, check, lib)
+                   OT_EDEVICE, OT_ENOMEM, OT_ETIME, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OT_PREC_BB,
+                   OT_PREC_SIMPLE, OTError, Options, Stats, check, lib)
 
 __all__ = ["Mesh", "State", "solve", "solve_batched", "options", "OTCost", "OTError", "Stats",
            "kprof_select", "kprof_read", "KPROF"]
@@ -59,6 +59,8 @@ def options(**kw):
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"mixed": OT_MIXED, "fp64": OT_FP64}[v]
+        if k == "preconditioner" and isinstance(v, str):
+            v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
@@ -75,6 +77,13 @@ class Mesh:
     def structured(cls, n, cartesian=False):
         h = C.c_void_p()
         check(lib().ot_mesh_create_structured(int(n), 1 if cartesian else 0, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def cartesian3d(cls, n):
+        """n^3 grid of cubes, J = identity (the three-dimensional workload)."""
+        h = C.c_void_p()
+        check(lib().ot_mesh_create_cartesian3d(int(n), C.byref(h)))
         return cls(h)
 
     @classmethod
@@ -168,6 +177,8 @@ class State:
         for k, v in kw.items():
             if k == "precision" and isinstance(v, str):
                 v = {"mixed": OT_MIXED, "fp64": OT_FP64}[v]
+            if k == "preconditioner" and isinstance(v, str):
+                v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE}[v]
             setattr(self.opt, k, v)
         check(lib().ot_state_set_options(self._h, C.byref(self.opt)))
 

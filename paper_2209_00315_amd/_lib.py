@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libotbb.so")
 OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG = 0, -1, -2, -3, -4
 OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM, OT_ETIME = -5, -6, -7, -8, -9
 OT_FP64, OT_MIXED = 0, 1
+OT_PREC_BB, OT_PREC_SIMPLE = 0, 1
 OT_HOST, OT_DEVICE = 0, 1
 
 ERROR_NAMES = {
@@ -32,7 +33,8 @@ class Options(C.Structure):
         ("final_tol", C.c_double), ("mu_stop", C.c_double), ("accept_relres", C.c_double),
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
         ("max_newton", C.c_int32), ("inner_restart", C.c_int32), ("max_inner_S", C.c_int32),
-        ("max_seconds", C.c_double), ("step_rule", C.c_int32),
+        ("eps_out_min", C.c_double), ("max_seconds", C.c_double), ("neighborhood", C.c_double),
+        ("preconditioner", C.c_int32), ("step_rule", C.c_int32),
         ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p),
     ]
@@ -46,7 +48,7 @@ class Stats(C.Structure):
         ("seconds_total", C.c_double), ("seconds_linear", C.c_double), ("seconds_setup", C.c_double),
         ("final_residual", C.c_double), ("mu", C.c_double),
         ("cost", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
-        ("last_relres", C.c_double),
+        ("last_relres", C.c_double), ("tightenings", C.c_int32),
     ]
 
     def as_dict(self):
@@ -71,6 +73,7 @@ SIGNATURES = {
     "ot_options_default": (None, [C.POINTER(Options)]),
     "ot_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
     "ot_mesh_create_structured": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    "ot_mesh_create_cartesian3d": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p)]),
     "ot_mesh_destroy": (None, [C.c_void_p]),
     "ot_mesh_sizes": (C.c_int, [C.c_void_p, iptr, iptr, iptr, iptr]),
     "ot_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(Options),
@@ -94,6 +97,7 @@ SIGNATURES = {
     "ot_state_solve": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(Stats)]),
     "ot_outputs": (C.c_int, [C.c_void_p, dptr, dptr, C.c_void_p]),
     "ot_last_error": (C.c_char_p, []),
+    "ot_abi_sizes": (None, [iptr, iptr, iptr]),
     "ot_kprof_select": (C.c_int, [C.c_int32, C.c_int32]),
     "ot_kprof_read": (C.c_int, [C.POINTER(C.c_int64), dptr, dptr]),
     "otbb_debug_structured_sizes": (C.c_int, [C.c_int32, C.c_int32, iptr]),
@@ -123,6 +127,15 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        # the structs passed by pointer must have the layout the library
+        # was built with (a stale build would read fields at wrong offsets)
+        sz = [C.c_int32() for _ in range(3)]
+        L.ot_abi_sizes(*[C.byref(x) for x in sz])
+        want = (C.sizeof(Options), C.sizeof(Stats), C.sizeof(MeshDesc))
+        got = tuple(x.value for x in sz)
+        if got != want:
+            raise RuntimeError(f"libotbb.so was built with struct sizes (options, stats, mesh_desc) {got}, the "
+                               f"binding declares {want}: rebuild with paper_2209_00315_amd.build.build()")
         _lib = L
     return _lib
 

@@ -34,7 +34,8 @@ int otbb_debug_structured_sizes(int32_t n, int32_t cartesian, int32_t out[8]) {
     return guard_dbg([&] {
         OT_REQUIRE(out, OT_EINVAL, "null argument");
         MeshHost h;
-        structured_desc(n, cartesian != 0, h);
+        if (cartesian == 3) cartesian3d_desc(n, h);
+        else structured_desc(n, cartesian != 0, h);
         derive_host_only(h);
         out[0] = h.nf; out[1] = h.nc; out[2] = h.ne; out[3] = h.nce;
         out[4] = (int32_t)h.ov_f.size(); out[5] = (int32_t)h.levels.size(); out[6] = h.ncolor; out[7] = h.wf;
@@ -47,7 +48,8 @@ int otbb_debug_structured_arrays(int32_t n, int32_t cartesian, int32_t *fe_cell,
                                  double *ce_dist, int32_t *color) {
     return guard_dbg([&] {
         MeshHost h;
-        structured_desc(n, cartesian != 0, h);
+        if (cartesian == 3) cartesian3d_desc(n, h);
+        else structured_desc(n, cartesian != 0, h);
         derive_host_only(h);
         for (int e = 0; e < h.ne; ++e) {
             if (fe_cell) { fe_cell[2 * e] = h.eK[e]; fe_cell[2 * e + 1] = h.eL[e]; }

@@ -198,21 +198,22 @@ __device__ __forceinline__ double ptx_at(const double *xr, const double *cs, dou
 
 // y_phi^k = A^k x_phi^k + (B^T w)^k with w = P^T x_rho, cs[l] = a'^T x_rho^l:
 // (B^T w)^k = Omega (w^{k-1} - w^k)/dt + 1/2 sum_e sgn len g_e R_E(w^{k-1} + w^k)_e
-__global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__ x,
-                             const double *__restrict__ cs, double *__restrict__ y) {
+// xphi == nullptr drops the A^k x_phi^k term (y = B^T P^T x_rho).
+__global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__ xphi,
+                             const double *__restrict__ xr, const double *__restrict__ cs,
+                             double *__restrict__ y) {
     const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     if (i >= m.nf) return;
     const int K = S.K, nc = m.nc;
-    const double *xp = x + (size_t)k * m.nf;
-    const double *xr = x + (size_t)(K + 1) * m.nf;
+    const double *xp = xphi ? xphi + (size_t)k * m.nf : nullptr;
     const double *ph = S.phi + (size_t)k * m.nf;
-    const double xi = xp[i];
+    const double xi = xp ? xp[i] : 0.0;
     double v = 0.0;
     for (int t = 0; t < m.wf; ++t) {
         const int e = m.cf_edge[t * m.nf + i];
         if (e < 0) break;
         const int nb = m.cf_nb[t * m.nf + i];
-        v += m.etw[e] * rho_edge(m, S, k, e) * (xi - xp[nb]);
+        if (xp) v += m.etw[e] * rho_edge(m, S, k, e) * (xi - xp[nb]);
         const double sgn = (m.eK[e] == i) ? 1.0 : -1.0;
         const int rK = m.erK[e], rL = m.erL[e];
         const double lam = m.elam[e];
@@ -229,11 +230,11 @@ __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__
     y[(size_t)k * m.nf + i] = v;
 }
 
-// u^k = (B x_phi)^k - C (P^T x_rho)^k  (C = a' s / rho); with_c = 0 drops C.
+// u^k = (B x_phi)^k - cfac C (P^T x_rho)^k  (C = a' s / rho); cfac = 0 drops C.
 // (B x)^k = Omega^T (x^{k+1} - x^k)/dt + 1/2 sum R_T-weights (g^k grad x^k + g^{k+1} grad x^{k+1})
 // Writes u and per-block partial slice sums of u (for the projector P).
 __global__ void k_opB(MeshView m, StateView S, const double *__restrict__ xphi,
-                      const double *__restrict__ xr, const double *__restrict__ cs, int with_c,
+                      const double *__restrict__ xr, const double *__restrict__ cs, double cfac,
                       double *__restrict__ u, double *__restrict__ part) {
     const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     double v = 0.0;
@@ -256,7 +257,7 @@ __global__ void k_opB(MeshView m, StateView S, const double *__restrict__ xphi,
         }
         v += 0.5 * g;
         const size_t q = (size_t)k * m.nc + j;
-        if (with_c) v -= m.ac[j] * S.s[q] / S.rho[q] * ptx_at(xr, cs, S.area, S.K, m.nc, k, j);
+        if (cfac != 0.0) v -= cfac * m.ac[j] * S.s[q] / S.rho[q] * ptx_at(xr, cs, S.area, S.K, m.nc, k, j);
         u[q] = v;
     }
     v = block_sum(v);
@@ -1116,6 +1117,53 @@ __global__ void k_ds_ratio(size_t n, StateView S, double mu, const double *__res
         part[blockIdx.x] = ap;
         part[gridDim.x + blockIdx.x] = ad;
     }
+}
+
+// Diagonal of the K+1 weighted Laplacians A^k (FP64): d^k_i = sum over the
+// edges of cell i of tw_e rho~^k_e (the SIMPLE approximation Diag(A)).
+__global__ void k_lap_diag(MeshView m, StateView S, double *__restrict__ d) {
+    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (i >= m.nf) return;
+    double v = 0.0;
+    for (int t = 0; t < m.wf; ++t) {
+        const int e = m.cf_edge[t * m.nf + i];
+        if (e < 0) break;
+        v += m.etw[e] * rho_edge(m, S, k, e);
+    }
+    d[(size_t)k * m.nf + i] = v;
+}
+
+// Largest step t in [0, amax] that keeps every cell in the neighbourhood
+// (rho + t drho)(s + t ds) >= gmu of the central path; per-block minima.
+// Per cell q(t) = a t^2 + b t + c with a = drho ds, b = rho ds + s drho,
+// c = rho s - gmu > 0, and the bound is its first positive root; cells
+// already outside the neighbourhood (c <= 0) do not constrain the step.
+__global__ void k_central_alpha(size_t n, StateView S, const double *__restrict__ drho,
+                                const double *__restrict__ ds, double gmu, double amax,
+                                double *__restrict__ part) {
+    double am = amax;
+    for (size_t q = (size_t)blockIdx.x * BS + threadIdx.x; q < n; q += (size_t)gridDim.x * BS) {
+        const double r = S.rho[q], s = S.s[q], dr = drho[q], d = ds[q];
+        const double c = r * s - gmu;
+        if (!(c > 0.0)) continue;
+        const double a = dr * d, b = r * d + s * dr;
+        double t = DBL_MAX;
+        if (a == 0.0) {
+            if (b < 0.0) t = -c / b;
+        } else {
+            const double disc = b * b - 4.0 * a * c;
+            if (disc >= 0.0) {
+                const double sq = sqrt(disc);
+                const double qq = -0.5 * (b + (b >= 0.0 ? sq : -sq));   // stable pair of roots
+                const double t1 = qq / a, t2 = c / qq;
+                if (t1 > 0.0) t = fmin(t, t1);
+                if (t2 > 0.0) t = fmin(t, t2);
+            }
+        }
+        am = fmin(am, t);
+    }
+    am = block_min(am);
+    if (threadIdx.x == 0) part[blockIdx.x] = am;
 }
 
 // x += alpha dx

@@ -121,6 +121,42 @@ void structured_desc(int n, bool cartesian, MeshHost &h) {
     h.celam.assign(h.nce, 0.5);
 }
 
+// The n x n x n grid of cubes on [0,1]^3 for both levels (J = identity): the
+// three-dimensional workload of Sec. 4.1.  Cell (c n + b) n + a; the TPFA
+// edges are the interior faces, |e| = h^2, d_e = h, lambda_e = 1/2, with K
+// the cell of smaller coordinate along the normal; volumes h^3.  The coarse
+// edges of the BB coarse Laplacian are the same faces.
+void cartesian3d_desc(int n, MeshHost &h) {
+    OT_REQUIRE(n >= 2 && n <= 1024, OT_EINVAL, "3-D Cartesian mesh: n must be in [2, 1024]");
+    h = MeshHost();
+    const double hh = 1.0 / n, vol = hh * hh * hh;
+    h.grid_n = n;
+    h.grid_dim = 3;
+    h.nf = h.nc = n * n * n;
+    h.a.assign(h.nf, vol);
+    h.ac.assign(h.nc, vol);
+    for (int i = 0; i < h.nf; ++i) { h.ov_f.push_back(i); h.ov_c.push_back(i); h.ov_a.push_back(vol); }
+    auto id = [n](int a, int b, int c) { return (c * n + b) * n + a; };
+    for (int c = 0; c < n; ++c)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a + 1 < n; ++a) { h.eK.push_back(id(a, b, c)); h.eL.push_back(id(a + 1, b, c)); }
+    for (int c = 0; c < n; ++c)
+        for (int b = 0; b + 1 < n; ++b)
+            for (int a = 0; a < n; ++a) { h.eK.push_back(id(a, b, c)); h.eL.push_back(id(a, b + 1, c)); }
+    for (int c = 0; c + 1 < n; ++c)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) { h.eK.push_back(id(a, b, c)); h.eL.push_back(id(a, b, c + 1)); }
+    h.ne = (int)h.eK.size();
+    h.erK = h.eK;
+    h.erL = h.eL;
+    h.elen.assign(h.ne, hh * hh);
+    h.edist.assign(h.ne, hh);
+    h.elam.assign(h.ne, 0.5);
+    h.ceI = h.eK; h.ceJ = h.eL;
+    h.celen = h.elen; h.cedist = h.edist; h.celam = h.elam;
+    h.nce = h.ne;
+}
+
 // ---------------------------------------------------------------------------
 // Validation
 // ---------------------------------------------------------------------------
@@ -186,8 +222,17 @@ static int pack_ell(const std::vector<std::vector<std::pair<int, T>>> &rows,
 // graphs a greedy root-plus-neighbours aggregation followed by attaching
 // leftovers to the neighbouring aggregate they share most edges with.
 static void aggregate(int n, int gridn, const std::vector<int> &ei, const std::vector<int> &ej,
-                      std::vector<int> &agg, int &nagg) {
+                      std::vector<int> &agg, int &nagg, int griddim = 2) {
     agg.assign(n, -1);
+    if (gridn > 0 && griddim == 3) {
+        int g2 = (gridn + 1) / 2;
+        for (int i = 0; i < n; ++i) {
+            int c = i / (gridn * gridn), r = i % (gridn * gridn), b = r / gridn, a = r % gridn;
+            agg[i] = ((c / 2) * g2 + b / 2) * g2 + a / 2;
+        }
+        nagg = g2 * g2 * g2;
+        return;
+    }
     if (gridn > 0) {
         int g2 = (gridn + 1) / 2;
         for (int i = 0; i < n; ++i) {
@@ -244,7 +289,7 @@ static void build_hierarchy(MeshHost &h) {
         bool last = n <= 4 || L.ne == 0;
         if (!last) {
             int nagg = 0;
-            aggregate(n, gridn, ei, ej, L.agg, nagg);
+            aggregate(n, gridn, ei, ej, L.agg, nagg, h.grid_dim);
             if (nagg >= n) last = true;
             else {
                 // members of each aggregate

@@ -44,7 +44,8 @@ struct SLevelDev {
 // Host copy of the description plus every derived index structure.
 struct MeshHost {
     int nf = 0, nc = 0, ne = 0, nce = 0;
-    int grid_n = 0;                    // > 0: fine cells form a grid_n^2 grid
+    int grid_n = 0;                    // > 0: fine cells form a grid_n^grid_dim grid
+    int grid_dim = 2;
     std::vector<double> a, ac;
     std::vector<int> ov_f, ov_c;
     std::vector<double> ov_a;
@@ -97,4 +98,5 @@ struct ot_mesh {
 namespace otbb {
 void mesh_finalize(ot_mesh *m);        // derive structures + upload
 void structured_desc(int n, bool cartesian, MeshHost &h);
+void cartesian3d_desc(int n, MeshHost &h);
 }  // namespace otbb

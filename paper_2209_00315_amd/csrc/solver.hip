@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -161,10 +162,11 @@ struct ot_state {
     DBuf<double> F, rhs, sol, gt, tmpN, tmpr, ds, sums, shift;
     DBuf<double> V, Z;
     Reducer red;
-    std::unique_ptr<PrecBase> prec;            // active preconditioner
+    // preconditioners built so far, by kind (2 * preconditioner + precision),
+    // kept for retries and switches; prec points at the active one
+    std::map<int, std::unique_ptr<PrecBase>> precs;
+    PrecBase *prec = nullptr;
     int prec_kind = -1;
-    std::unique_ptr<PrecBase> prec_alt;        // the other precision, kept for retries
-    int prec_alt_kind = -1;
     bool lin_valid = false;
     ot_stats acc{};
     // last FGMRES info
@@ -224,29 +226,40 @@ static double residual(ot_state *st) {
     return std::sqrt(st->red.fetch(d, 1)[0]);
 }
 
-// y = J_P x (both length N, device)
-static void apply_saddle(ot_state *st, const double *x, double *y) {
+// y = J_P x (both length N, device), with caller-provided scratch: sums
+// (2 (K + 2) doubles) and part (block partials), on stream s
+static void apply_saddle_core(const ot_state *st, const double *x, double *y, double *sums, double *part,
+                              hipStream_t s) {
     const ot_mesh *m = st->mesh;
     MeshView mv = mesh_view(m);
     StateView sv = st->view();
     const int K = st->K, nf = m->h.nf, nc = m->h.nc;
-    double *cs = st->sums.p;                 // a'^T x_rho^k
-    double *us = st->sums.p + K + 2;         // 1^T u^k
-    slice_sums<double>(st, x + st->nphi, m->ac, nc, K, cs);
+    double *cs = sums;                       // a'^T x_rho^k
+    double *us = sums + K + 2;               // 1^T u^k
+    {
+        const int nblk = std::min(256, std::max(1, ceil_div(nc, BS)));
+        k_seg_partial<double><<<dim3(nblk, K), BS, 0, s>>>(x + st->nphi, m->ac, nc, part);
+        k_seg_final<<<K, BS, 0, s>>>(part, nblk, cs);
+    }
     {
         // x, phi, y over the potential block; x_rho and rho once; geometry once
         const MeshHost &h = m->h;
         const double bytes = 8.0 * (3.0 * st->nphi + 2.0 * st->mrho) + 8.0 * h.wf * nf + 12.0 * h.wo * nf +
                              40.0 * h.ne;
         const kprof::Ev ev = kprof::take(OT_KPROF_SADDLE_PHI, 8, bytes);
-        hipExtLaunchKernelGGL(k_saddle_phi, grid2(nf, K + 1), dim3(BS), 0, st->stream, ev.a, ev.b, 0, mv, sv, x,
-                              (const double *)cs, y);
+        hipExtLaunchKernelGGL(k_saddle_phi, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, sv, x,
+                              x + st->nphi, (const double *)cs, y);
     }
     dim3 gc = grid2(nc, K);
-    k_opB<<<gc, BS, 0, st->stream>>>(mv, sv, x, x + st->nphi, cs, 1, y + st->nphi, st->red.part);
-    k_seg_final<<<K, BS, 0, st->stream>>>(st->red.part, gc.x, us);
-    k_proj_fix<double><<<gc, BS, 0, st->stream>>>(m->ac, nc, us, st->area, y + st->nphi);
+    k_opB<<<gc, BS, 0, s>>>(mv, sv, x, x + st->nphi, cs, 1.0, y + st->nphi, part);
+    k_seg_final<<<K, BS, 0, s>>>(part, gc.x, us);
+    k_proj_fix<double><<<gc, BS, 0, s>>>(m->ac, nc, us, st->area, y + st->nphi);
 }
+
+static void apply_saddle(ot_state *st, const double *x, double *y) {
+    apply_saddle_core(st, x, y, st->sums.p, st->red.part.p, st->stream);
+}
+
 
 // ---------------------------------------------------------------------------
 // Krylov helpers
@@ -817,21 +830,168 @@ struct BBPrec : PrecBase {
     }
 };
 
+// ---------------------------------------------------------------------------
+// SIMPLE preconditioner (Sec. 4.3) on the projected system, FP64
+// ---------------------------------------------------------------------------
+// P^-1 (c; d): u = D^-1 c with D = Diag(A); v = d - P B u; y solves
+// P (C + B D^-1 B^T) P^T y = -v (the negative of the approximate Schur
+// complement S~ = -(C + B D^-1 B^T), projected); x = u - D^-1 B^T P^T y.
+// The inner system is symmetric positive semidefinite with the per-slice
+// constants as kernel and a consistent right-hand side; it is solved by PCG
+// to eps_in_S (cap max_inner) with the exact time-line tridiagonal part of
+// C + B D^-1 B^T as preconditioner (probed, like the pseudo-Schur time
+// diagonals of the BB preconditioner).
+struct SimplePrec : PrecBase {
+    int nf = 0, nc = 0, K = 0;
+    size_t nphi = 0, mrho = 0;
+    DBuf<double> dA, u, tphi, bu, v, y, r, z, p, q, w, probe, d0, dl, du, inv_dd, lm, up, zsum;
+
+    void alloc(ot_state *st) {
+        const ot_mesh *m = st->mesh;
+        nf = m->h.nf; nc = m->h.nc; K = st->K;
+        nphi = st->nphi; mrho = st->mrho;
+        dA.alloc(nphi); u.alloc(nphi); tphi.alloc(nphi);
+        for (DBuf<double> *b : {&bu, &v, &y, &r, &z, &p, &q, &w, &probe, &d0, &dl, &du, &inv_dd, &lm, &up})
+            b->alloc(mrho);
+        zsum.alloc(K + 2);
+    }
+
+    // out = (C + B D^-1 B^T) P^T x (project = true) or (C + B D^-1 B^T) x,
+    // then P applied to the result when project is set
+    void opX(ot_state *st, const double *x, double *out, bool project) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        StateView sv = st->view();
+        double *cs = st->sums.p + 5 * (K + 2);           // a'^T x^k (for P^T x)
+        if (project) slice_sums<double>(st, x, m->ac, nc, K, cs);
+        else k_fill<double><<<1, BS, 0, s>>>(cs, K + 2, 0.0);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, x, cs, tphi.p);      // B^T P^T x
+        k_dscale<double><<<grid1(nphi), BS, 0, s>>>(nphi, dA, 1, tphi, tphi);               // D^-1
+        dim3 gc = grid2(nc, K);
+        k_opB<<<gc, BS, 0, s>>>(mv, sv, tphi, x, cs, -1.0, out, st->red.part);              // B (.) + C P^T x
+        if (project) {
+            double *us = st->sums.p + 6 * (K + 2);
+            k_seg_final<<<K, BS, 0, s>>>(st->red.part, gc.x, us);
+            k_proj_fix<double><<<gc, BS, 0, s>>>(m->ac, nc, us, st->area, out);
+        }
+    }
+
+    void setup(ot_state *st) override {
+        if (nf == 0) alloc(st);
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        k_lap_diag<<<grid2(nf, K + 1), BS, 0, s>>>(mesh_view(m), st->view(), dA);
+        // time-line tridiagonal part of C + B D^-1 B^T by probing (the colouring
+        // separates cells coupled through the fine cells around their overlaps)
+        dim3 gc = grid2(nc, K);
+        k_fill<double><<<grid1(mrho), BS, 0, s>>>(dl, mrho, 0.0);
+        k_fill<double><<<grid1(mrho), BS, 0, s>>>(du, mrho, 0.0);
+        for (int tc = 0; tc < std::min(3, K); ++tc)
+            for (int c = 0; c < m->h.ncolor; ++c) {
+                k_probe<double><<<gc, BS, 0, s>>>(nc, m->color, tc, c, probe);
+                opX(st, probe, q, false);
+                k_probe_scatter<double><<<gc, BS, 0, s>>>(nc, K, m->color, tc, c, q, d0, dl, du);
+            }
+        k_tri_factor<double><<<grid1(nc, 1 << 20), BS, 0, s>>>(nc, K, d0, dl, du, inv_dd, lm, up);
+    }
+
+    void tri(ot_state *st, const double *rr, double *x) {
+        if (K <= kTriScanMaxK)
+            k_tri_scan<double, 0><<<ceil_div(nc, BS / 64), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, rr, x);
+        else
+            k_tri_solve<double, 0><<<grid1(nc, 1 << 20), BS, 0, st->stream>>>(nc, K, inv_dd, lm, up, rr, x);
+    }
+
+    double dot(ot_state *st, const double *a, const double *b) {
+        double *out = st->sums.p + 7 * (K + 2);
+        const int nblk = std::min(256, std::max(1, ceil_div((int64_t)mrho, BS)));
+        k_seg_dot_partial<double><<<dim3(nblk, 1), BS, 0, st->stream>>>(a, b, (int)mrho, st->red.part);
+        k_seg_final<<<1, BS, 0, st->stream>>>(st->red.part, nblk, out);
+        return st->red.fetch(out, 1)[0];
+    }
+
+    // PCG on P X P^T y = b (b consistent), y = 0 start; returns iterations
+    int pcg(ot_state *st, const double *b, double tol, int maxit) {
+        hipStream_t s = st->stream;
+        k_fill<double><<<grid1(mrho), BS, 0, s>>>(y, mrho, 0.0);
+        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(b, r, mrho);
+        const double bn = std::sqrt(std::max(dot(st, r, r), 0.0));
+        if (bn == 0.0) return 0;
+        tri(st, r, z);
+        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(z, p, mrho);
+        double rz = dot(st, r, z);
+        int it = 0;
+        for (it = 1; it <= maxit; ++it) {
+            opX(st, p, q, true);
+            const double pq = dot(st, p, q);
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, alpha, p, 1.0, y);
+            k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -alpha, q, 1.0, r);
+            const double rn = std::sqrt(std::max(dot(st, r, r), 0.0));
+            if (rn <= tol * bn) break;
+            tri(st, r, z);
+            const double rz2 = dot(st, r, z);
+            k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, 1.0, z, rz2 / rz, p);
+            rz = rz2;
+        }
+        return std::min(it, maxit);
+    }
+
+    void apply(ot_state *st, const double *rin, double *zout) override {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        StateView sv = st->view();
+        dim3 gc = grid2(nc, K);
+        // u = D^-1 c; v = -(d - P B u) (the right-hand side of P X P^T y = -v)
+        k_dscale<double><<<grid1(nphi), BS, 0, s>>>(nphi, dA, 1, rin, u);
+        k_opB<<<gc, BS, 0, s>>>(mv, sv, u, nullptr, nullptr, 0.0, bu, st->red.part);
+        double *us = st->sums.p + 4 * (K + 2);
+        k_seg_final<<<K, BS, 0, s>>>(st->red.part, gc.x, us);
+        k_proj_fix<double><<<gc, BS, 0, s>>>(m->ac, nc, us, st->area, bu.p);              // P B u
+        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(bu, v, mrho);
+        k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -1.0, rin + nphi, 1.0, v);       // P B u - d
+        st->acc.inner_S_iters += pcg(st, v, st->opt.eps_in_S, st->opt.max_inner);
+        // x = u - D^-1 B^T P^T y; z = (x; y)
+        double *cs = st->sums.p + 5 * (K + 2);
+        slice_sums<double>(st, y.p, m->ac, nc, K, cs);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, y, cs, tphi.p);
+        k_dscale<double><<<grid1(nphi), BS, 0, s>>>(nphi, dA, 1, tphi, tphi);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(u, zout, nphi);
+        k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, -1.0, tphi, 1.0, zout);
+        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(y, zout + nphi, mrho);
+        st->acc.prec_applies++;
+    }
+
+    // component access of the BB preconditioner: not part of SIMPLE
+    void schur_apply_d(ot_state *, const double *, double *) override { unsupported(); }
+    int schur_solve_d(ot_state *, const double *, double *, double, int) override { unsupported(); return 0; }
+    void tri_diagonals_d(ot_state *, double *, double *, double *) override { unsupported(); }
+    void tri_solve_d(ot_state *, const double *, double *) override { unsupported(); }
+    int laplace_solve_d(ot_state *, const double *, double *, double, int) override { unsupported(); return 0; }
+    void vcycle_d(ot_state *, const double *, double *) override { unsupported(); }
+    size_t level_data_d(ot_state *, int, int, double *) override { unsupported(); return 0; }
+    static void unsupported() {
+        throw OtError(OT_EINVAL, "inspection call of the BB preconditioner on a state using SIMPLE");
+    }
+};
+
 namespace otbb {
 
 static void ensure_prec(ot_state *st) {
-    int kind = st->opt.precision;
-    if (!st->prec || st->prec_kind != kind) {
-        std::swap(st->prec, st->prec_alt);
-        std::swap(st->prec_kind, st->prec_alt_kind);
-        st->lin_valid = false;
+    const int kind = 2 * st->opt.preconditioner + (st->opt.preconditioner == OT_PREC_SIMPLE ? OT_FP64 : st->opt.precision);
+    if (st->prec && st->prec_kind == kind) return;
+    std::unique_ptr<PrecBase> &slot = st->precs[kind];
+    if (!slot) {
+        if (st->opt.preconditioner == OT_PREC_SIMPLE) slot.reset(new SimplePrec());
+        else if (st->opt.precision == OT_MIXED) slot.reset(new BBPrec<float>());
+        else slot.reset(new BBPrec<double>());
     }
-    if (!st->prec || st->prec_kind != kind) {
-        if (kind == OT_MIXED) st->prec.reset(new BBPrec<float>());
-        else st->prec.reset(new BBPrec<double>());
-        st->prec_kind = kind;
-        st->lin_valid = false;
-    }
+    st->prec = slot.get();
+    st->prec_kind = kind;
+    st->lin_valid = false;
 }
 
 static void linearize(ot_state *st) {
@@ -860,7 +1020,21 @@ static void ensure_cols(ot_state *st, DBuf<double> &B, int cols, int cap) {
     B = std::move(nb);
 }
 
-static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int maxit, double *res_out) {
+// Tightening rule of the outer solve: once FGMRES meets its tolerance, the
+// step length of the trial direction is evaluated; while it is below
+// alpha_ok (and still grew by 10% since the last check), the tolerance is
+// divided by 100, down to tol_floor_abs, and the iteration continues in the
+// same Krylov space.  Near the positivity boundary a direction that meets
+// eps_out can still be wrong by more than rho in a few cells, which caps
+// the step length; the Newton iteration then crawls at steps of 1e-2.
+struct TightenRule {
+    std::function<double(const double *)> alpha;   // step length of direction x
+    double alpha_ok = 0.9;
+    double tol_floor_abs = 0.0;
+};
+
+static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int maxit, double *res_out,
+                  const TightenRule *tr = nullptr) {
     hipStream_t s = st->stream;
     const size_t N = st->N;
     const int m = std::max(1, std::min(st->opt.restart, maxit));
@@ -874,40 +1048,59 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
     int its = 0;
     double res = beta;
     std::vector<double> h(m + 1), hist;
-    bool stop = false;
+    bool stop = false, first_cycle = true;
+    double alpha_prev = -1.0;
     const double beta0 = beta;
     while (its < maxit) {
         k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, st->V.p, 1.0 / beta, st->V.p);
         G.reset(beta);
         int j = 0;
-        for (; j < m && its < maxit; ++j) {
-            ensure_cols(st, st->Z, j + 1, m);
-            ensure_cols(st, st->V, j + 2, m + 1);
-            double *zj = st->Z.p + (size_t)j * N;
-            st->prec->apply(st, st->V.p + (size_t)j * N, zj);
-            double *wn = st->V.p + (size_t)(j + 1) * N;
-            apply_saddle(st, zj, wn);
-            double hn = cgs2<double>(st, st->V.p, N, j + 1, wn, N, h.data());
-            for (int i = 0; i <= j; ++i) G.h(i, j) = h[i];
-            G.h(j + 1, j) = hn;
-            ++its;
-            res = G.push(j);
-            if (hn > 0) k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, wn, 1.0 / hn, wn);
-            if (st->opt.verbose > 1) fprintf(stderr, "    fgmres it %d res %.3e target %.3e\n", its, res, tol_abs);
-            hist.push_back(res);
-            // plateau: no halving over the last 40 iterations (after 80) once
-            // the residual is already within accept_relres of the initial
-            // one, where the step is taken anyway: near a converged Newton
-            // iterate the residual meets the rounding floor of the operator
-            // well above eps_out |b|, and the cap would only add time
-            const bool stalled = its >= 80 && res > 0.5 * hist[its - 41] && res <= st->opt.accept_relres * beta0;
-            if (res <= tol_abs || hn == 0.0 || stalled) { stop = stalled; ++j; break; }
+        for (;;) {
+            bool breakdown = false;
+            for (; j < m && its < maxit; ++j) {
+                ensure_cols(st, st->Z, j + 1, m);
+                ensure_cols(st, st->V, j + 2, m + 1);
+                double *zj = st->Z.p + (size_t)j * N;
+                st->prec->apply(st, st->V.p + (size_t)j * N, zj);
+                double *wn = st->V.p + (size_t)(j + 1) * N;
+                apply_saddle(st, zj, wn);
+                double hn = cgs2<double>(st, st->V.p, N, j + 1, wn, N, h.data());
+                for (int i = 0; i <= j; ++i) G.h(i, j) = h[i];
+                G.h(j + 1, j) = hn;
+                ++its;
+                res = G.push(j);
+                if (hn > 0) k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 0.0, wn, 1.0 / hn, wn);
+                if (st->opt.verbose > 1) fprintf(stderr, "    fgmres it %d res %.3e target %.3e\n", its, res, tol_abs);
+                hist.push_back(res);
+                // plateau: no halving over the last 40 iterations (after 80) once
+                // the residual is already within accept_relres of the initial
+                // one, where the step is taken anyway: near a converged Newton
+                // iterate the residual meets the rounding floor of the operator
+                // well above eps_out |b|, and the cap would only add time
+                const bool stalled = its >= 80 && res > 0.5 * hist[its - 41] && res <= st->opt.accept_relres * beta0;
+                if (res <= tol_abs || hn == 0.0 || stalled) { stop = stalled; breakdown = hn == 0.0; ++j; break; }
+            }
+            // x = x_cycle_start + Z y; the first cycle starts from x = 0
+            std::vector<double> y = G.solve(j);
+            OT_HIP(hipMemcpyAsync(st->shift.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+            k_combine<double, double><<<grid1(N), BS, 0, s>>>(N, st->Z.p, N, j, st->shift.p, first_cycle ? 0.0 : 1.0, x);
+            OT_HIP(hipStreamSynchronize(s));
+            if (tr && first_cycle && res <= tol_abs && !stop && !breakdown && j < m && its < maxit &&
+                tol_abs > tr->tol_floor_abs) {
+                const double a = tr->alpha(x);
+                if (st->opt.verbose)
+                    fprintf(stderr, "    fgmres %d its at tol %.2e: trial step %.3f\n", its, tol_abs / beta0, a);
+                if (a < tr->alpha_ok && (alpha_prev < 0.0 || a > 1.1 * alpha_prev)) {
+                    alpha_prev = a;
+                    tol_abs = std::max(0.01 * tol_abs, tr->tol_floor_abs);
+                    st->acc.tightenings++;
+                    continue;                       // same Krylov space, tighter target
+                }
+            }
+            break;
         }
-        std::vector<double> y = G.solve(j);
-        OT_HIP(hipMemcpyAsync(st->shift.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-        k_combine<double, double><<<grid1(N), BS, 0, s>>>(N, st->Z.p, N, j, st->shift.p, 1.0, x);
-        OT_HIP(hipStreamSynchronize(s));
         if (res <= tol_abs || its >= maxit || stop) break;
+        first_cycle = false;
         // restart with the true residual
         apply_saddle(st, x, st->V.p);
         k_axpby<double><<<grid1(N), BS, 0, s>>>(N, 1.0, b, -1.0, st->V.p);
@@ -922,7 +1115,27 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
 // Solve J_s (dphi; drho) = (f; g~) through the projected system and the
 // recovery of Sec. 4.4.1-2.  rhs holds (f; g~) on entry (g~ also in gt);
 // solution written to sol.  Returns FGMRES iterations; sets last_converged.
-static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
+// Step length min(1, tau alpha_max) that the trial solution sol of the
+// projected system would give (the common rule): drho = P^T drho_hat,
+// ds = (h - s drho) / rho, largest step keeping rho and s positive.  Leaves
+// the state untouched (scratch: tmpr, ds, sums, reduction buffers).
+static double trial_alpha(ot_state *st, const double *sol) {
+    const ot_mesh *m = st->mesh;
+    hipStream_t s = st->stream;
+    const int K = st->K, nc = m->h.nc;
+    double *cs = st->sums.p + 6 * (K + 2);
+    slice_sums<double>(st, sol + st->nphi, m->ac, nc, K, cs);
+    k_convert<double, double><<<grid1(st->mrho), BS, 0, s>>>(sol + st->nphi, st->tmpr.p, st->mrho);
+    k_slice_shift<double><<<grid2(nc, K), BS, 0, s>>>(nc, cs, 1.0 / st->area, st->tmpr.p);
+    const int nblk = grid1(st->mrho);
+    k_ds_ratio<<<nblk, BS, 0, s>>>(st->mrho, st->view(), st->mu, st->tmpr.p, st->ds, st->red.part);
+    k_min_final<<<1, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
+    k_min_final<<<1, BS, 0, s>>>(st->red.part.p + nblk, nblk, st->red.dev.p + 1);
+    const double *am = st->red.fetch(st->red.dev, 2);
+    return std::min(1.0, st->opt.frac_to_boundary * std::min(am[0], am[1]));
+}
+
+static int solve_newton_system(ot_state *st, double rhs_norm_abs, bool tighten = false) {
     const ot_mesh *m = st->mesh;
     hipStream_t s = st->stream;
     const int K = st->K, nf = m->h.nf, nc = m->h.nc;
@@ -936,7 +1149,11 @@ static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
     double t0 = now_s();
     double res = 0.0;
     const double tol = st->opt.eps_out * rhs_norm_abs;
-    int its = fgmres(st, st->rhs, st->sol, tol, st->opt.max_fgmres, &res);
+    TightenRule rule;
+    rule.alpha = [st](const double *x) { return trial_alpha(st, x); };
+    rule.tol_floor_abs = st->opt.eps_out_min * rhs_norm_abs;
+    const bool use_rule = tighten && st->opt.eps_out_min < st->opt.eps_out;
+    int its = fgmres(st, st->rhs, st->sol, tol, st->opt.max_fgmres, &res, use_rule ? &rule : nullptr);
     st->acc.seconds_linear += now_s() - t0;
     st->acc.outer_iters += its;
     st->acc.linear_systems++;
@@ -952,7 +1169,7 @@ static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
     slice_sums<double>(st, dphi, m->a, nf, K + 1, ps);
     k_slice_shift<double><<<grid2(nf, K + 1), BS, 0, s>>>(nf, ps, 1.0 / st->area, dphi);
     dim3 gc = grid2(nc, K);
-    k_opB<<<gc, BS, 0, s>>>(mv, sv, dphi, nullptr, nullptr, 0, st->tmpr, nullptr);
+    k_opB<<<gc, BS, 0, s>>>(mv, sv, dphi, nullptr, nullptr, 0.0, st->tmpr, nullptr);
     k_recover_r<<<gc, BS, 0, s>>>(nc, m->ac, st->gt, st->tmpr, drho, sv, st->red.part);
     double *ls = st->sums.p + 2 * (K + 2);
     k_seg_final<<<K, BS, 0, s>>>(st->red.part, gc.x, ls);
@@ -971,8 +1188,8 @@ static int solve_newton_system(ot_state *st, double rhs_norm_abs) {
 // failure policy for the linear solves; the paper reports such failures
 // and stops).  strict: retry whenever eps_out was missed.  The right-hand
 // side is untouched by a solve, so the retry starts from the same system.
-static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = false) {
-    solve_newton_system(st, rhs_norm_abs);
+static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = false, bool tighten = false) {
+    solve_newton_system(st, rhs_norm_abs, tighten);
     if (st->last_converged || (!strict && st->last_relres <= st->opt.accept_relres)) return;
     const ot_options saved = st->opt;
     const int its1 = st->last_iters;
@@ -982,7 +1199,7 @@ static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = fa
     st->opt.eps_in_A = 0.1 * saved.eps_in_A;
     st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
     linearize(st);
-    solve_newton_system(st, rhs_norm_abs);
+    solve_newton_system(st, rhs_norm_abs, tighten);
     st->acc.linear_systems--;              // one Newton system, two attempts
     if (st->opt.verbose)
         fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1, st->last_iters,
@@ -1018,7 +1235,7 @@ static int newton_step(ot_state *st, double *res_before) {
     linearize(st);
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
-    solve_with_retry(st, fn);
+    solve_with_retry(st, fn, false, true);
     int rc = OT_OK;
     if (!st->last_converged) {
         st->acc.failures++;
@@ -1037,12 +1254,41 @@ static int newton_step(ot_state *st, double *res_before) {
     k_min_final<<<1, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
     k_min_final<<<1, BS, 0, s>>>(st->red.part.p + nblk, nblk, st->red.dev.p + 1);
     const double *am = st->red.fetch(st->red.dev, 2);
+    if (st->opt.verbose > 2) {
+        // where the step length is decided: the cells with the smallest
+        // -rho/drho and -s/ds (host copies, diagnostics only)
+        std::vector<double> r(st->mrho), dr(st->mrho), sv(st->mrho), dsv(st->mrho);
+        OT_HIP(hipMemcpyAsync(r.data(), st->rho.p, st->mrho * 8, hipMemcpyDeviceToHost, s));
+        OT_HIP(hipMemcpyAsync(dr.data(), drho, st->mrho * 8, hipMemcpyDeviceToHost, s));
+        OT_HIP(hipMemcpyAsync(sv.data(), st->s.p, st->mrho * 8, hipMemcpyDeviceToHost, s));
+        OT_HIP(hipMemcpyAsync(dsv.data(), st->ds.p, st->mrho * 8, hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+        for (int which = 0; which < 2; ++which) {
+            const std::vector<double> &x = which ? sv : r, &dx = which ? dsv : dr;
+            std::vector<std::pair<double, size_t>> lim;
+            for (size_t q = 0; q < st->mrho; ++q)
+                if (dx[q] < 0) lim.push_back({-x[q] / dx[q], q});
+            std::partial_sort(lim.begin(), lim.begin() + std::min<size_t>(4, lim.size()), lim.end());
+            for (size_t t = 0; t < std::min<size_t>(4, lim.size()); ++t) {
+                const size_t q = lim[t].second;
+                fprintf(stderr, "    limit %s: ratio %.3e at level %zu cell %zu: rho %.3e drho %.3e s %.3e ds %.3e\n",
+                        which ? "s" : "rho", lim[t].first, q / nc, q % nc, r[q], dr[q], sv[q], dsv[q]);
+            }
+        }
+    }
     const double tau = st->opt.frac_to_boundary;
     const double a_p = std::min(1.0, tau * am[0]), a_d = std::min(1.0, tau * am[1]);
     // OT_STEP_COMMON: one step for (phi, rho, s); OT_STEP_SPLIT: phi and rho
     // take the largest step keeping rho positive, s its own
     const bool split = st->opt.step_rule == OT_STEP_SPLIT;
-    const double alpha = std::min(a_p, a_d);
+    double alpha = std::min(a_p, a_d);
+    if (st->opt.neighborhood > 0.0 && !split) {
+        // keep (rho, s) in the neighbourhood rho s >= gamma mu of the central path
+        k_central_alpha<<<nblk, BS, 0, s>>>(st->mrho, sv, drho, st->ds, st->opt.neighborhood * st->mu, alpha,
+                                           st->red.part);
+        k_min_final<<<1, BS, 0, s>>>(st->red.part, nblk, st->red.dev);
+        alpha = std::min(alpha, st->red.fetch(st->red.dev, 1)[0]);
+    }
     const double alpha_p = split ? a_p : alpha, alpha_d = split ? a_d : alpha;
     k_axpy<<<grid1(st->nphi), BS, 0, s>>>(st->nphi, alpha_p, st->sol, st->phi);
     k_axpy<<<grid1(st->mrho), BS, 0, s>>>(st->mrho, alpha_p, drho, st->rho);
@@ -1143,11 +1389,14 @@ void check_options(const ot_options &o) {
     OT_REQUIRE(o.frac_to_boundary > 0 && o.frac_to_boundary < 1, OT_EINVAL, "bad step fraction");
     OT_REQUIRE(o.accept_relres >= 0 && o.accept_relres < 1, OT_EINVAL, "bad accept_relres");
     OT_REQUIRE(o.max_seconds >= 0.0, OT_EINVAL, "max_seconds must be >= 0");
+    OT_REQUIRE(o.neighborhood >= 0.0 && o.neighborhood < 1.0, OT_EINVAL, "neighborhood must be in [0, 1)");
+    OT_REQUIRE(o.eps_out_min > 0, OT_EINVAL, "eps_out_min must be > 0");
     OT_REQUIRE(o.max_fgmres >= 1 && o.restart >= 1 && o.restart < kMaxBasis && o.max_inner >= 1 && o.max_inner_S >= 1 &&
                    (o.step_rule == OT_STEP_COMMON || o.step_rule == OT_STEP_SPLIT) && o.mu_stop >= 0.0 &&
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
                OT_EINVAL, "bad iteration caps");
     OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
+    OT_REQUIRE(o.preconditioner == OT_PREC_BB || o.preconditioner == OT_PREC_SIMPLE, OT_EINVAL, "bad preconditioner");
     OT_REQUIRE(o.mem_kind == OT_HOST || o.mem_kind == OT_DEVICE, OT_EINVAL, "bad mem_kind");
 }
 
@@ -1256,14 +1505,23 @@ void ot_options_default(ot_options *o) {
     o->tol = 1e-6; o->eps_out = 1e-5; o->eps_in_S = 1e-1; o->eps_in_A = 1e-6;
     o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0; o->mu_stop = 0.0;
     o->accept_relres = 1e-2;
+    o->eps_out_min = 1e-10;
     o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 60; o->inner_restart = 30;
     o->max_inner_S = 10;
     o->max_seconds = 0.0;
+    o->neighborhood = 0.0;
+    o->preconditioner = OT_PREC_BB;
     o->step_rule = OT_STEP_COMMON;
     o->precision = OT_MIXED; o->mem_kind = OT_HOST; o->verbose = 0; o->stream = nullptr;
 }
 
 const char *ot_last_error(void) { return g_last_error.c_str(); }
+
+void ot_abi_sizes(int32_t *options_bytes, int32_t *stats_bytes, int32_t *mesh_desc_bytes) {
+    if (options_bytes) *options_bytes = (int32_t)sizeof(ot_options);
+    if (stats_bytes) *stats_bytes = (int32_t)sizeof(ot_stats);
+    if (mesh_desc_bytes) *mesh_desc_bytes = (int32_t)sizeof(ot_mesh_desc);
+}
 
 int ot_kprof_select(int32_t kernel, int32_t elem_bytes) {
     return guard([&] {
@@ -1336,6 +1594,17 @@ int ot_mesh_create_structured(int32_t n, int32_t cartesian, ot_mesh **out) {
     });
 }
 
+int ot_mesh_create_cartesian3d(int32_t n, ot_mesh **out) {
+    return guard([&] {
+        OT_REQUIRE(out, OT_EINVAL, "null argument");
+        *out = nullptr;
+        std::unique_ptr<ot_mesh> m(new ot_mesh());
+        cartesian3d_desc(n, m->h);
+        mesh_finalize(m.get());
+        *out = m.release();
+    });
+}
+
 void ot_mesh_destroy(ot_mesh *m) { delete m; }
 
 int ot_mesh_sizes(const ot_mesh *m, int32_t *nf, int32_t *nc, int32_t *ne, int32_t *nce) {
@@ -1377,10 +1646,9 @@ int ot_state_set_options(ot_state *st, const ot_options *opt) {
         const int old_inner = st->opt.inner_restart;
         st->opt = *opt;
         if (old_inner != opt->inner_restart) {     // inner basis size is fixed at allocation
-            st->prec.reset();
+            st->prec = nullptr;
             st->prec_kind = -1;
-            st->prec_alt.reset();
-            st->prec_alt_kind = -1;
+            st->precs.clear();
         }
         st->lin_valid = false;
     });
@@ -1449,6 +1717,7 @@ int ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm) {
             stats->linear_systems -= before.linear_systems;
             stats->newton_steps -= before.newton_steps;
             stats->failures -= before.failures;
+            stats->tightenings -= before.tightenings;
         }
         if (rc != OT_OK) set_last_error("FGMRES did not reach eps_out");
     });
@@ -1537,6 +1806,7 @@ int ot_state_solve(ot_state *st, double tol, ot_stats *stats) {
             stats->inner_A_iters -= before.inner_A_iters;
             stats->prec_applies -= before.prec_applies;
             stats->failures -= before.failures;
+            stats->tightenings -= before.tightenings;
             stats->seconds_total -= before.seconds_total;
             stats->seconds_linear -= before.seconds_linear;
             stats->seconds_setup -= before.seconds_setup;

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import otinputs
-from oracle.mesh import structured_mesh, cartesian_mesh, mesh_from_arrays
+from oracle.mesh import structured_mesh, cartesian_mesh, cartesian3d_mesh, mesh_from_arrays
 from oracle.ipm import Problem, residual, solve_ipm, newton_step, renormalize, initial_point
 from oracle.bb import projected_matrix, apply_bb_exact
 from oracle.gradient import cost_gradient
@@ -49,6 +49,7 @@ CASES = [
     ("tri16K8", lambda: structured_mesh(16), lambda: ot.Mesh.structured(16), 8),
     ("cart6K1", lambda: cartesian_mesh(6), lambda: ot.Mesh.structured(6, cartesian=True), 1),
     ("tri2K2", lambda: structured_mesh(2), lambda: ot.Mesh.structured(2), 2),
+    ("cube4K3", lambda: cartesian3d_mesh(4), lambda: ot.Mesh.cartesian3d(4), 3),
 ]
 
 
@@ -163,6 +164,28 @@ def test_full_solve_gaussian16(precision):
     ctol, ftol = (1e-6, 1e-5) if precision == "fp64" else (1e-5, 1e-4)
     assert cost_err < ctol and rho_err < ftol and phi_err < ftol
     assert st.ip_steps == 10 and st.failures == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_solve_cube8(precision):
+    """The three-dimensional workload at its first size: 8^3 cubes, K+1 = 8,
+    Gaussians of variance 0.1 at (0.3, 0.3, 0.3) -> (0.7, 0.7, 0.7)."""
+    n, K = 8, 7
+    ri, rf = otinputs.gaussian3d_pair(n)
+    _say(f"[full solve cube n={n} K={K} {precision}]")
+    prob = Problem(cartesian3d_mesh(n), K, ri, rf)
+    ref = solve_ipm(prob, tol=1e-6, final_tol=1e-10)
+    out = ot.solve(ot.Mesh.cartesian3d(n), ri, rf, K, tol=1e-6, final_tol=1e-10, precision=precision)
+    st = out["stats"]
+    cost_err = abs(out["cost"] - ref.cost) / ref.cost
+    ac, a = prob.ops.ac, prob.ops.a
+    rho_err = _norm_a(out["rho"].reshape(K, -1) - ref.rho, ac[None, :]) / _norm_a(ref.rho, ac[None, :])
+    phi_err = _norm_a(out["phi"].reshape(K + 1, -1) - ref.phi, a[None, :]) / _norm_a(ref.phi, a[None, :])
+    _say(f"  cost {out['cost']:.12f} ref {ref.cost:.12f} rel {cost_err:.2e} rho {rho_err:.2e} phi {phi_err:.2e} "
+         f"newton {st.newton_steps} outer {st.outer_iters}")
+    ctol, ftol = (1e-6, 1e-5) if precision == "fp64" else (1e-5, 1e-4)
+    assert out["rc"] == ot.OT_OK
+    assert cost_err < ctol and rho_err < ftol and phi_err < ftol
 
 
 def test_full_solve_generic_mesh():

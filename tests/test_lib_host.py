@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import otinputs
-from oracle.mesh import structured_mesh, cartesian_mesh
+from oracle.mesh import structured_mesh, cartesian_mesh, cartesian3d_mesh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -97,10 +97,10 @@ def _arrays(n, cart):
                 color=color)
 
 
-@pytest.mark.parametrize("n,cart", [(2, 0), (4, 0), (16, 0), (6, 1), (8, 1)])
+@pytest.mark.parametrize("n,cart", [(2, 0), (4, 0), (16, 0), (6, 1), (8, 1), (2, 3), (5, 3)])
 def test_cpp_mesh_matches_oracle_mesh(n, cart):
     d = _arrays(n, cart)
-    m = (cartesian_mesh if cart else structured_mesh)(n)
+    m = {0: structured_mesh, 1: cartesian_mesh, 3: cartesian3d_mesh}[cart](n)
     assert (d["nf"], d["nc"], d["ne"], d["nce"]) == (m.n_fine, m.n_coarse, m.n_fedge, m.n_cedge)
     key = lambda K, L, rK, rL: sorted(zip(K.tolist(), L.tolist(), rK.tolist(), rL.tolist()))
     assert key(d["fe_cell"][:, 0], d["fe_cell"][:, 1], d["fe_rho"][:, 0], d["fe_rho"][:, 1]) == \

@@ -109,6 +109,36 @@ def test_split_step_rule_reaches_same_solution(gaussian16):
         solve_ipm(prob, tol=1e-6, step_rule="bogus")
 
 
+def test_neighborhood_rule_reaches_same_solution(gaussian16):
+    """The central-path neighbourhood step rule (rho s >= gamma mu kept in
+    every cell) changes the path only: the solution of the final relaxed
+    system is unique."""
+    prob, r = gaussian16
+    r2 = solve_ipm(prob, tol=1e-6, final_tol=1e-11, neighborhood=0.1)
+    assert r2.converged
+    assert abs(r2.cost - r.cost) < 1e-9 * r.cost
+    assert np.abs(r2.rho - r.rho).max() < 1e-7 * np.abs(r.rho).max()
+
+
+def test_central_step_keeps_products_above_bound():
+    """central_step against a brute-force scan of the step length."""
+    from oracle.ipm import central_step
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.1, 2.0, 50)
+    s = rng.uniform(0.1, 2.0, 50)
+    drho = rng.standard_normal(50)
+    ds = rng.standard_normal(50)
+    gmu = 0.05
+    t = central_step(rho, s, drho, ds, gmu, 1.0)
+    ok = (rho * s) > gmu
+    grid = np.linspace(0.0, 1.0, 20001)
+    prod = (rho[ok, None] + grid[None, :] * drho[ok, None]) * (s[ok, None] + grid[None, :] * ds[ok, None])
+    feasible = np.all(prod >= gmu, axis=0)
+    t_scan = grid[np.argmin(feasible)] if not feasible.all() else 1.0
+    assert abs(t - t_scan) <= 1.0 / 20000 + 1e-12
+    assert np.all((rho[ok] + t * drho[ok]) * (s[ok] + t * ds[ok]) >= gmu * (1 - 1e-12))
+
+
 def test_uniform_marginals_closed_form():
     """rho_in = rho_f = 1: rho = 1, s = mu, phi^k = -(k-1) dt mu + c, KE = 0."""
     for mk in (structured_mesh, cartesian_mesh):
