@@ -269,6 +269,26 @@ int  ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm);
 int  ot_apply_saddle(ot_state *st, const double *x, double *y);
 
 /*
+ * Allocation-free y = J_P x, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operator and kernels as ot_apply_saddle, but x and y are always
+ * device pointers (whatever opt.mem_kind says), the work is queued on
+ * `stream` (NULL: the state's stream) without any host synchronisation, and
+ * the kernels' scratch (slice sums and per-block partial sums) lives in a
+ * library-held device array of 1 MiB per GPU (131072 doubles) instead of
+ * the state's workspaces.  The call allocates nothing and calls no
+ * allocating routine; the scratch array of a GPU is held until the process
+ * ends.  Limit: 2 (K + 2) + ceil(n_coarse / 256) K <= 131072.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in
+ * time on one GPU (different streams or threads) race, so serialise them.
+ * The scratch needs no clearing: every value is written before it is read.
+ * The state's device must be current.
+ * Errors: OT_EINVAL (null pointer, problem above the limit, wrong current
+ * device), OT_EDEVICE.
+ */
+int  ot_apply_saddle_noalloc(const ot_state *st, const double *x, double *y, void *stream);
+
+/*
  * z = P_BB^-1 r: one application of the BB preconditioner (Sec. 4.4.3)
  * linearised at the current state: pseudo-Schur solve
  * (Diag(s) A~ - Diag(rho) B M^-1 B~) w = -Diag(rho) P r_rho, then

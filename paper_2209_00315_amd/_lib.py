@@ -92,6 +92,7 @@ SIGNATURES = {
     "ot_residual": (C.c_int, [C.c_void_p, C.c_void_p, dptr]),
     "ot_newton_step": (C.c_int, [C.c_void_p, C.POINTER(Stats), dptr]),
     "ot_apply_saddle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ot_apply_saddle_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_apply_schur_prec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ot_state_solve": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(Stats)]),

@@ -7,6 +7,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -226,6 +227,14 @@ static double residual(ot_state *st) {
     return std::sqrt(st->red.fetch(d, 1)[0]);
 }
 
+// Scratch of y = J_P x: two slice-sum vectors (K each) and the per-block
+// partial sums of the larger of its two reductions.
+static size_t saddle_scratch_doubles(const ot_state *st) {
+    const size_t K = st->K, nc = st->mesh->h.nc;
+    const size_t nblk = std::max<size_t>(std::min<size_t>(256, (nc + BS - 1) / BS), (nc + BS - 1) / BS);
+    return 2 * (K + 2) + nblk * K;
+}
+
 // y = J_P x (both length N, device), with caller-provided scratch: sums
 // (2 (K + 2) doubles) and part (block partials), on stream s
 static void apply_saddle_core(const ot_state *st, const double *x, double *y, double *sums, double *part,
@@ -260,6 +269,32 @@ static void apply_saddle(ot_state *st, const double *x, double *y) {
     apply_saddle_core(st, x, y, st->sums.p, st->red.part.p, st->stream);
 }
 
+// ---------------------------------------------------------------------------
+// Library-held scratch for the entry point that allocates nothing
+// (ot_apply_saddle_noalloc).  One copy per device, held until the process
+// ends; its device address is looked up once per device with that device
+// current (the array's name is only a host-side handle).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocScratch = 131072;            // doubles (1 MiB)
+static __device__ __align__(256) double scratch[kNoallocScratch];
+constexpr int kMaxDevices = 64;
+static double *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device (looked up on first use)
+static double *scratch_on_current_device() {
+    int dev = -1;
+    OT_HIP(hipGetDevice(&dev));
+    OT_REQUIRE(dev >= 0 && dev < kMaxDevices, OT_EDEVICE, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        OT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        OT_REQUIRE(p != nullptr, OT_EDEVICE, "no device address for the scratch array");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    return g_scratch_dev[dev];
+}
 
 // ---------------------------------------------------------------------------
 // Krylov helpers
@@ -1456,6 +1491,8 @@ ot_state *create_state(const ot_mesh *m, const double *rho_in, const double *rho
     size_t np = (size_t)(ceil_div(std::max(std::max(nf, nc), std::max(m->h.ne, 1)), BS) + 1) * (2 * K + 4) +
                 (size_t)kMaxBasis * kMultidotBlocks;
     st->red.init(np, std::max<size_t>(2 * kMaxBasis + 1, 8 * (size_t)(K + 2)), s);
+    // set-up of the allocation-free entry point on this device
+    (void)scratch_on_current_device();
     // start point: phi = 0, rho = m0/|Omega|, s = mu0/rho
     k_fill<double><<<grid1(st->nphi), BS, 0, s>>>(st->phi, st->nphi, 0.0);
     k_fill<double><<<grid1(st->mrho), BS, 0, s>>>(st->rho, st->mrho, st->m0 / st->area);
@@ -1732,6 +1769,23 @@ int ot_apply_saddle(ot_state *st, const double *x, double *y) {
         apply_saddle(st, st->tmpN, st->rhs);
         copy_out(y, st->rhs, st->N, mk, st->stream);
         OT_HIP(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ot_apply_saddle_noalloc(const ot_state *st, const double *x, double *y, void *stream) {
+    return guard([&] {
+        OT_REQUIRE(st && x && y, OT_EINVAL, "null argument");
+        int dev = -1;
+        OT_HIP(hipGetDevice(&dev));
+        OT_REQUIRE(dev == st->mesh->device, OT_EINVAL, "the state's device must be current");
+        const size_t need = saddle_scratch_doubles(st);
+        OT_REQUIRE(need <= kNoallocScratch, OT_EINVAL,
+                   "problem too large for the library scratch of ot_apply_saddle_noalloc: needs " +
+                       std::to_string(need) + " doubles, holds " + std::to_string(kNoallocScratch));
+        double *sc = scratch_on_current_device();
+        hipStream_t s = stream ? (hipStream_t)stream : st->stream;
+        apply_saddle_core(st, x, y, sc, sc + 2 * (size_t)(st->K + 2), s);
+        OT_HIP(hipGetLastError());
     });
 }
 
