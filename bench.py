@@ -43,10 +43,10 @@ SAMPLE_N, SAMPLE_K = 24, 12
 COPY_BYTES = 1 << 30          # reference copy of the counter loop: 1 GiB read, 1 GiB written
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
 # `bench.py --counter-loop 20` (KiB per dispatch), scaled by what the same
-# counters read for the 1 GiB reference copy; valid only for the kernel
-# version those runs measured, on the 256 x 256, K = 64 workload (None: not
-# measured for the current kernel).
-TRAFFIC_BYTES = {}
+# counters read for the 1 GiB reference copy (fetch x2.0000, write x1.0000);
+# profiles/k_schur_out_256x256_K64_traffic.md.  Valid only for the kernel
+# version those runs measured, on the 256 x 256, K = 64 workload.
+TRAFFIC_BYTES = {("schur_out", 3): 73632.9 * 1024 * 2.0 + 8192.0 * 1024 * 1.0}
 KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 METRIC = "time-to-tol (s) & Krylov iters/s, 256^2 mesh K=64: mixed vs FP64, 1 GPU"
@@ -63,6 +63,9 @@ def parse():
                    help="wall seconds (from process start) by which the line must be printed")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 time to tolerance")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--tol-only", choices=("mixed", "fp64"), default=None,
+                   help="only the time to tolerance of one precision, with the whole budget (no timed steps, "
+                        "no CPU sample); prints its own JSON line")
     p.add_argument("--verbose", type=int, default=0)
     p.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--counter-loop", type=int, default=0,
@@ -181,12 +184,14 @@ def main():
             if mu < 1e-6:
                 break
             mu *= 0.2
-        its = systems = newton = fails = 0
+        its = systems = newton = fails = simple = 0
         rc, mu_done = ot.OT_OK, None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for mu_l in mus:
-            if snapshots is not None and mu_l < 1.0:
+            # snapshots only while every system so far was solved with BB:
+            # the timed steps measure the BB-preconditioned path
+            if snapshots is not None and mu_l < 1.0 and simple == 0:
                 # the converged iterate of the previous mu, with mu reduced
                 phi, rho, s, _ = st.export()
                 snapshots.append((phi, rho, s, mu_l))
@@ -200,11 +205,12 @@ def main():
             systems += stt.linear_systems
             newton += stt.newton_steps
             fails += stt.failures
+            simple += stt.simple_systems
             if rc != ot.OT_OK:
                 break
             mu_done = stt.mu
             log(f"{prec}: mu {mu_l:.3e} solved: Newton {stt.newton_steps} FGMRES {stt.outer_iters} "
-                f"t {time.perf_counter() - t0:.1f}s")
+                f"SIMPLE systems {stt.simple_systems} t {time.perf_counter() - t0:.1f}s")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         cost, dual, _ = st.outputs()
@@ -212,7 +218,15 @@ def main():
         return {"reached": reached, "time_to_tol_s": dt if reached else None, "seconds_run": dt, "rc": rc,
                 "mu_last_solved": mu_done, "newton_steps": newton, "linear_systems": systems,
                 "outer_iters": its, "krylov_its_per_s": its / dt if dt > 0 else None, "failures": fails,
+                "simple_systems": simple,
                 "cost": cost, "gap": cost - dual, "limit_s": limit}
+
+    if a.tol_only:
+        r = time_to_tol(a.tol_only, max(30.0, remaining() - 15.0))
+        print(json.dumps({"metric": "time-to-tol (s), " + METRIC.split(", ", 1)[1], "precision": a.tol_only,
+                          "value": r["time_to_tol_s"], "unit": "s", "higher_is_better": False,
+                          "config": {"n": n, "K": K, "config": a.config}, **r, "wall_s": elapsed()}), flush=True)
+        return
 
     snaps = []
     share = 0.38 if not a.no_fp64 else 0.6
@@ -273,7 +287,8 @@ def main():
                                   f"benchmark configuration {a.config}"),
                    "n": n, "K": K, "unknowns_per_newton_system": int((K + 1) * n * n + K * (n * n // 2)),
                    "step": "one inexact Newton step of the mixed path from a snapshot iterate (the first "
-                           "Newton system of each interior-point step reached), snapshots in turn",
+                           "Newton system of each interior-point step reached while the continuation "
+                           "still ran on the BB preconditioner), snapshots in turn",
                    "snapshots_mu": [x[3] for x in snaps]},
         "time_to_tol_s": mixed["time_to_tol_s"],
         "mixed": mixed,

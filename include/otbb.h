@@ -66,6 +66,7 @@ extern "C" {
 
 #define OT_PREC_BB     0   /* BB block-triangular preconditioner (Sec. 4.4.3) */
 #define OT_PREC_SIMPLE 1   /* SIMPLE preconditioner (Sec. 4.3), FP64       */
+#define OT_PREC_HYBRID 2   /* BB, handing over to SIMPLE when BB degrades  */
 
 #define OT_HOST   0
 #define OT_DEVICE 1
@@ -112,15 +113,17 @@ typedef struct {
  *  FGMRES pays for once mu is small: 1e-6 cuts its iterations up to 8x;
  *  FP32 vectors still reach it),
  *  mu0 1, mu_factor 0.2, step fraction 0.99, caps 400 FGMRES / 200 inner
- *  (Laplacian PCG) / 10 pseudo-Schur GMRES / 60 Newton per mu (the
- *  pseudo-Schur solve stops at eps_in_S or at its cap, whichever comes
- *  first: past ~10 iterations its extra accuracy no longer lowers the
- *  FGMRES count; the paper gives no Newton cap, and fine grids with
- *  near-empty regions need up to ~30 steps at one mu), restart 400
+ *  (Laplacian PCG, SIMPLE's inner PCG) / 10 pseudo-Schur GMRES / 20 Newton
+ *  per mu (the pseudo-Schur solve stops at eps_in_S or at its cap,
+ *  whichever comes first: past ~10 iterations its extra accuracy no longer
+ *  lowers the FGMRES count; the paper gives no Newton cap and reports 3-7
+ *  steps per mu, which the step-length tightening of eps_out and the
+ *  hybrid preconditioner below reproduce on the benchmark grids), restart 400
  *  (FGMRES runs unrestarted within its cap, as in Sec. 4; its basis grows
  *  on demand up to (restart + 1) + restart vectors of N doubles), inner
- *  restart 30, accept_relres 1e-2, OT_STEP_COMMON, OT_MIXED, OT_HOST,
- *  null stream.
+ *  restart 30, accept_relres 1e-2, eps_out_min 1e-10, OT_STEP_COMMON,
+ *  neighborhood 0, OT_PREC_HYBRID, hybrid_alpha 0.5, batch_streams 8,
+ *  OT_MIXED, OT_HOST, null stream, no time limit.
  */
 typedef struct {
     double tol, eps_out, eps_in_S, eps_in_A;
@@ -152,7 +155,15 @@ typedef struct {
                                 rho s >= gamma mu (a neighbourhood of the
                                 central path, keeping the next Newton system
                                 well scaled); 0 (default): positivity only */
-    int32_t preconditioner;  /* OT_PREC_BB (default) or OT_PREC_SIMPLE: the
+    int32_t preconditioner;  /* OT_PREC_HYBRID (default), OT_PREC_BB or
+                                OT_PREC_SIMPLE.  OT_PREC_HYBRID uses BB until
+                                a Newton system whose BB solve misses eps_out
+                                with a direction that the positivity line
+                                search would cut below hybrid_alpha, or ends
+                                above accept_relres; that system and every
+                                later one of the state (until
+                                ot_state_import) are solved with SIMPLE.
+                                OT_PREC_SIMPLE: the
                                 SIMPLE preconditioner of Sec. 4.3 on the
                                 projected system, u = Diag(A)^-1 c,
                                 P (C + B Diag(A)^-1 B^T) P^T y = P B u - d
@@ -160,6 +171,11 @@ typedef struct {
                                 exact time-line tridiagonal part as
                                 preconditioner, x = u - Diag(A)^-1 B^T P^T y;
                                 always FP64 (precision applies to BB)      */
+    double hybrid_alpha;     /* step-length threshold of OT_PREC_HYBRID
+                                (default 0.5)                               */
+    int32_t batch_streams;   /* ot_solve_batched: members solved at once,
+                                each on its own stream and host thread
+                                (default 8; 1 = one after another)         */
     int32_t step_rule;       /* OT_STEP_COMMON (default): one step length for
                                 (phi, rho, s), the largest that keeps rho and
                                 s positive times frac_to_boundary (Sec. 2.4);
@@ -180,6 +196,7 @@ typedef struct {
     double cost, dual, gap;
     double last_relres;      /* FGMRES relative residual of the last system  */
     int32_t tightenings;     /* FGMRES tolerance tightenings (eps_out_min)   */
+    int32_t simple_systems;  /* Newton systems solved with SIMPLE            */
 } ot_stats;
 
 void ot_options_default(ot_options *opt);
@@ -219,10 +236,15 @@ int  ot_solve(const ot_mesh *mesh, const double *rho_in, const double *rho_f,
               double *rho_out, double *phi_out, double *cost_out, ot_stats *stats);
 
 /*
- * Solve nprob independent problems (meshes and K may differ), one after
- * another on opt->stream, each with its own state as in ot_solve.  Arrays
- * of pointers have nprob entries; costs[nprob]; stats[nprob] or NULL.  All
- * members are attempted; the return value is the first member's error.
+ * Solve nprob independent problems (meshes and K may differ), each with its
+ * own state and its own convergence as in ot_solve.  Up to
+ * opt->batch_streams members run at the same time, each on a stream of the
+ * library's own (created and destroyed by this call) driven by one host
+ * thread; opt->stream is synchronised before the members start, and the
+ * call returns when every member is done.  Arrays of pointers have nprob
+ * entries; costs[nprob]; stats[nprob] or NULL.  All members are attempted;
+ * the return value is the error of the lowest-numbered failing member
+ * (ot_last_error names it).
  */
 int  ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes,
                       const double *const *rho_in, const double *const *rho_f,

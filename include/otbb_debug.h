@@ -62,10 +62,21 @@ int otbb_debug_schur_solve(ot_state *st, const double *rhs, double *z, double to
 int otbb_debug_tri_diagonals(ot_state *st, double *d0, double *dl, double *du);
 int otbb_debug_tri_solve(ot_state *st, const double *r, double *x);
 /* Time levels per thread of the two time-blocked pseudo-Schur passes for
- * FP32 (elem_bytes 4), FP64 (8) or both (0) operands (process-wide tuning
- * knob; 0 levels = one level per thread; the defaults are 16 / 0 in FP32
- * and 16 / 16 in FP64). */
+ * FP32 (elem_bytes 4), FP64 (8) or both (0) operands, for the BB
+ * preconditioners created afterwards (process-wide knob; 0 levels = one
+ * level per thread).  By default each preconditioner times the candidates
+ * 0, 4, 8, 16, 32 on its own mesh and K at its first linearisation and keeps
+ * the fastest; this call fixes the values instead, and both values negative
+ * returns to the autotuner. */
 int otbb_debug_set_schur_blocking(int32_t elem_bytes, int32_t btilde_levels, int32_t out_levels);
+/* V-cycle of the pseudo-Schur multigrid (Sec. 4.4.3 solves that system
+ * iteratively; the multigrid is this library's own) for the BB
+ * preconditioners created afterwards (process-wide knob): damping omega of
+ * the time-line Jacobi smoother in (0, 1], nu pre- and post-smoothing steps
+ * in [1, 16], coarse_its smoothing steps on the coarsest level in [1, 200],
+ * alpha in (0, 3] scales the prolongated coarse correction.  Defaults
+ * 0.5, 2, 6, 1.0.  OT_EINVAL for values out of range. */
+int otbb_debug_set_schur_mg(double omega, int32_t nu, int32_t coarse_its, double alpha);
 int otbb_debug_laplace_solve(ot_state *st, const double *b, double *x, double tol, int32_t maxit,
                              int32_t *iters);
 int otbb_debug_vcycle(ot_state *st, const double *b, double *x);

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libotbb.so")
 OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG = 0, -1, -2, -3, -4
 OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM, OT_ETIME = -5, -6, -7, -8, -9
 OT_FP64, OT_MIXED = 0, 1
-OT_PREC_BB, OT_PREC_SIMPLE = 0, 1
+OT_PREC_BB, OT_PREC_SIMPLE, OT_PREC_HYBRID = 0, 1, 2
 OT_HOST, OT_DEVICE = 0, 1
 
 ERROR_NAMES = {
@@ -34,7 +34,8 @@ class Options(C.Structure):
         ("max_fgmres", C.c_int32), ("restart", C.c_int32), ("max_inner", C.c_int32),
         ("max_newton", C.c_int32), ("inner_restart", C.c_int32), ("max_inner_S", C.c_int32),
         ("eps_out_min", C.c_double), ("max_seconds", C.c_double), ("neighborhood", C.c_double),
-        ("preconditioner", C.c_int32), ("step_rule", C.c_int32),
+        ("preconditioner", C.c_int32), ("hybrid_alpha", C.c_double),
+        ("batch_streams", C.c_int32), ("step_rule", C.c_int32),
         ("precision", C.c_int32), ("mem_kind", C.c_int32), ("verbose", C.c_int32),
         ("stream", C.c_void_p),
     ]
@@ -48,7 +49,7 @@ class Stats(C.Structure):
         ("seconds_total", C.c_double), ("seconds_linear", C.c_double), ("seconds_setup", C.c_double),
         ("final_residual", C.c_double), ("mu", C.c_double),
         ("cost", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
-        ("last_relres", C.c_double), ("tightenings", C.c_int32),
+        ("last_relres", C.c_double), ("tightenings", C.c_int32), ("simple_systems", C.c_int32),
     ]
 
     def as_dict(self):
@@ -109,6 +110,7 @@ SIGNATURES = {
     "otbb_debug_schur_apply": (C.c_int, [C.c_void_p, dptr, dptr]),
     "otbb_debug_tri_solve": (C.c_int, [C.c_void_p, dptr, dptr]),
     "otbb_debug_set_schur_blocking": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
+    "otbb_debug_set_schur_mg": (C.c_int, [C.c_double, C.c_int32, C.c_int32, C.c_double]),
     "otbb_debug_schur_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),
     "otbb_debug_tri_diagonals": (C.c_int, [C.c_void_p, dptr, dptr, dptr]),
     "otbb_debug_laplace_solve": (C.c_int, [C.c_void_p, dptr, dptr, C.c_double, C.c_int32, iptr]),

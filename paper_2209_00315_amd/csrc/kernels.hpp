@@ -341,6 +341,7 @@ __global__ void k_gs_update(size_t n, const T *__restrict__ V, size_t ldv, int n
     double sq = 0.0;
     for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
         double wi = (double)w[i];
+#pragma unroll 8
         for (int v = 0; v < nv; ++v) wi -= h[v] * (double)V[(size_t)v * ldv + i];
         const T wt = (T)wi;
         w[i] = wt;
@@ -1047,12 +1048,12 @@ __global__ void k_sdiag(SLevelView L, int K, const T *__restrict__ v, double *__
 }
 
 template <typename T>
-__global__ void k_sprolong(int n, int n_next, const int *__restrict__ agg, const T *__restrict__ xc,
+__global__ void k_sprolong(int n, int n_next, const int *__restrict__ agg, const T *__restrict__ xc, double w,
                            T *__restrict__ x) {
     const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     if (j >= n) return;
     const size_t q = (size_t)k * n + j;
-    x[q] = (T)((double)x[q] + (double)xc[(size_t)k * n_next + agg[j]]);
+    x[q] = (T)((double)x[q] + w * (double)xc[(size_t)k * n_next + agg[j]]);
 }
 
 // ----------------------------------------------------- Newton step pieces

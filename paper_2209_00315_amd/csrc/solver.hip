@@ -6,6 +6,8 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <thread>
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -65,13 +67,27 @@ Ev take_slot(double bytes) {
 // inner_restart are validated against it); sizes every Krylov scratch.
 constexpr int kMaxBasis = 401;
 constexpr int kMultidotBlocks = 512;
+constexpr int kUpdateBlocks = 8192;
 // time levels per thread of the two time-blocked pseudo-Schur passes
 // (M^-1 B~ z, output) for FP32 [0] and FP64 [1] operands; 0 selects the
 // one-level-per-thread kernels.  Measured at 256^2, K = 64: blocking by 16
 // cuts the FP32 M^-1 B~ z pass from 72 to 28 us and the FP64 passes from
 // 83 / 103 to 53 / 65 us, while the FP32 output pass is fastest unblocked
 // (76 us; blocked 92-128 us, fewer independent gathers in flight).
+// These are the defaults; each BB preconditioner measures the candidates on
+// its own mesh and K at its first linearisation (autotune_schur_blocking)
+// unless otbb_debug_set_schur_blocking has fixed them.
 static int g_schur_tb[2][2] = {{16, 0}, {16, 16}};
+static bool g_schur_tb_fixed[2] = {false, false};
+// pseudo-Schur V-cycle parameters of BB preconditioners created afterwards
+// (otbb_debug_set_schur_mg)
+struct SchurMGParams {
+    double omega = 0.5;          // damping of the time-line Jacobi smoother
+    int nu = 2;                  // pre- and post-smoothing steps
+    int coarse_its = 6;          // smoothing steps on the coarsest level
+    double alpha = 1.0;          // scale of the prolongated coarse correction
+};
+static SchurMGParams g_smg;
 // longest time line the wavefront-scan tridiagonal solve handles
 constexpr int kTriScanMaxK = 64 * kern::kTriScanChunks;
 
@@ -168,6 +184,7 @@ struct ot_state {
     std::map<int, std::unique_ptr<PrecBase>> precs;
     PrecBase *prec = nullptr;
     int prec_kind = -1;
+    bool hybrid_simple = false;                // OT_PREC_HYBRID has switched to SIMPLE
     bool lin_valid = false;
     ot_stats acc{};
     // last FGMRES info
@@ -307,9 +324,10 @@ static double cgs2(ot_state *st, const T *V, size_t ld, int nv, T *w, size_t n, 
     Reducer &R = st->red;
     OT_REQUIRE(nv >= 1 && nv <= kMaxBasis, OT_EINVAL, "internal: Krylov basis too large");
     const int nblk = grid1(n, kMultidotBlocks);
+    const int nblk_u = grid1(n, kUpdateBlocks);
     const int ng = (nv + 7) / 8;
-    OT_REQUIRE(R.part.n >= (size_t)nv * nblk && R.dev.n >= 2 * (size_t)kMaxBasis + 1, OT_EINVAL,
-               "internal: reduction scratch too small");
+    OT_REQUIRE(R.part.n >= std::max((size_t)nv * nblk, (size_t)nblk_u) && R.dev.n >= 2 * (size_t)kMaxBasis + 1,
+               OT_EINVAL, "internal: reduction scratch too small");
     double *h1 = R.dev.p, *h2 = R.dev.p + kMaxBasis, *nr = R.dev.p + 2 * kMaxBasis;
     for (int pass = 0; pass < 2; ++pass) {
         double *hp = pass ? h2 : h1;
@@ -319,9 +337,11 @@ static double cgs2(ot_state *st, const T *V, size_t ld, int nv, T *w, size_t n, 
                                   nv, (const T *)w, R.part.p);
         }
         k_seg_final<<<nv, BS, 0, st->stream>>>(R.part, nblk, hp);
-        k_gs_update<T><<<nblk, BS, 0, st->stream>>>(n, V, ld, nv, hp, w, R.part);
+        // the update walks all nv vectors per element: give it the whole
+        // vector length in blocks so that every CU keeps loads in flight
+        k_gs_update<T><<<nblk_u, BS, 0, st->stream>>>(n, V, ld, nv, hp, w, R.part);
     }
-    k_seg_final<<<1, BS, 0, st->stream>>>(R.part, nblk, nr);
+    k_seg_final<<<1, BS, 0, st->stream>>>(R.part, nblk_u, nr);
     const double *hh = R.fetch(R.dev.p, 2 * kMaxBasis + 1);
     for (int i = 0; i < nv; ++i) h[i] = hh[i] + hh[kMaxBasis + i];
     return std::sqrt(std::max(hh[2 * kMaxBasis], 0.0));
@@ -389,9 +409,10 @@ struct BBPrec : PrecBase {
     int nsl = 0;
     std::vector<DBuf<T>> sv, sinv, slm, sup, sb, sx, sr, stt;
     DBuf<double> sd0, sdl, sdu;                // coarse-level diagonal scratch
-    double somega = 0.5;
+    double somega = 0.5, s_alpha = 1.0;         // smoother damping, coarse-correction scale
     int s_nu = 2, s_coarse_its = 6;
     int mS = 20;
+    int tb_b = -1, tb_o = -1;                  // pseudo-Schur pass blocking (autotuned)
     const double hi = 2.0, lo_ratio = 0.3, coarse_lo_ratio = 0.02;
     int nu = 2, coarse_deg = 8;
     // Over-correction of the piecewise-constant coarse-grid correction: plain
@@ -405,6 +426,7 @@ struct BBPrec : PrecBase {
         nphi = st->nphi; mrho = st->mrho;
         nlev = (int)m->lv.size();
         mS = std::max(2, st->opt.inner_restart);
+        somega = g_smg.omega; s_nu = g_smg.nu; s_coarse_its = g_smg.coarse_its; s_alpha = g_smg.alpha;
         g.alloc((size_t)(K + 1) * std::max(ne, 1));
         wc.alloc((size_t)K * std::max(nce, 1));
         rhoT.alloc(mrho); sT.alloc(mrho);
@@ -509,7 +531,7 @@ struct BBPrec : PrecBase {
         s_apply(st, l, x, b, sr[l]);
         k_srestrict<T><<<grid2(L.n_next, K), BS, 0, s>>>(L.n_next, L.n, L.mem_ptr, L.mem_idx, sr[l], sb[l + 1]);
         s_vcycle(st, l + 1, sb[l + 1], sx[l + 1]);
-        k_sprolong<T><<<grid2(L.n, K), BS, 0, s>>>(L.n, L.n_next, L.agg, sx[l + 1], x);
+        k_sprolong<T><<<grid2(L.n, K), BS, 0, s>>>(L.n, L.n_next, L.agg, sx[l + 1], s_alpha, x);
         for (int it = 0; it < s_nu; ++it) {
             s_apply(st, l, x, b, sr[l]);
             s_tri(st, l, sr[l], stt[l]);
@@ -550,6 +572,7 @@ struct BBPrec : PrecBase {
         if (nce > 0) k_lin_cedges<T><<<grid2(nce, K), BS, 0, s>>>(mv, sv, wc);
         k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->rho, rhoT, mrho);
         k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->s, sT, mrho);
+        if (tb_b < 0) autotune_schur_blocking(st);
         for (int l = 0; l < nlev; ++l) {
             const MGLevelDev &L = m->lv[l];
             if (l > 0) {
@@ -585,9 +608,23 @@ struct BBPrec : PrecBase {
         const MeshHost &h = m->h;
         // time-blocked passes (levels per thread; 0 = per-level kernels) when
         // the cell stencils fit their register caps
-        const bool fits = h.wf <= kTbWF && h.wo <= kTbWO && h.woc <= kTbWOC && h.wr <= kTbWR && h.wcc <= kTbWCC;
-        const int *tbl = g_schur_tb[sizeof(T) == 8 ? 1 : 0];
-        const int tb_btilde = fits ? tbl[0] : 0, tb_out = fits ? tbl[1] : 0;
+        const int tb_btilde = blocking_fits(m) ? tb_b : 0, tb_out = blocking_fits(m) ? tb_o : 0;
+        launch_btilde(st, z, tb_btilde);
+        launch_out(st, z, out, tb_out);
+    }
+
+    static bool blocking_fits(const ot_mesh *m) {
+        const MeshHost &h = m->h;
+        return h.wf <= kTbWF && h.wo <= kTbWO && h.woc <= kTbWOC && h.wr <= kTbWR && h.wcc <= kTbWCC;
+    }
+
+    // pass 2 of the pseudo-Schur operator, v = M^-1 B~ z (u from pass 1)
+    void launch_btilde(ot_state *st, const T *z, int tb_btilde) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        const double b = sizeof(T), S1 = K + 1;
+        const MeshHost &h = m->h;
         {
             // z, u, g, v once; overlap, cell-edge and edge geometry once
             const double bytes = b * ((double)K * nc + 2.0 * S1 * nf + S1 * ne) +
@@ -601,6 +638,15 @@ struct BBPrec : PrecBase {
                 hipExtLaunchKernelGGL(k_schur_btilde<T>, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, K,
                                       st->dt, z, (const T *)uT.p, (const T *)g.p, vT.p);
         }
+    }
+
+    // pass 3, out = s (A~ z) - rho (B v)
+    void launch_out(ot_state *st, const T *z, T *out, int tb_out) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        const double b = sizeof(T), S1 = K + 1;
+        const MeshHost &h = m->h;
         {
             // z, v, g, w~, rho, s, out once; coarse-cell geometry once
             const double bytes = b * (4.0 * K * nc + S1 * nf + S1 * ne + (double)K * nce) + 8.0 * h.wcc * nc +
@@ -615,6 +661,51 @@ struct BBPrec : PrecBase {
                                       z, (const T *)vT.p, (const T *)g.p, (const T *)wc.p, (const T *)rhoT.p,
                                       (const T *)sT.p, out);
         }
+    }
+
+    // Autotuner of the time blocking (levels per thread) of passes 2 and 3:
+    // each candidate is timed with HIP events on this preconditioner's own
+    // mesh, K and precision (3 launches each, after one untimed launch) and
+    // the fastest kept.  Runs once, at the first linearisation.
+    void autotune_schur_blocking(ot_state *st) {
+        const int r = sizeof(T) == 8 ? 1 : 0;
+        tb_b = g_schur_tb[r][0];
+        tb_o = g_schur_tb[r][1];
+        if (g_schur_tb_fixed[r] || !blocking_fits(st->mesh)) return;
+        hipStream_t s = st->stream;
+        k_fill<T><<<grid1(mrho), BS, 0, s>>>(probe, mrho, (T)1);
+        k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mesh_view(st->mesh), K, probe, uT);
+        hipEvent_t e0, e1;
+        OT_HIP(hipEventCreate(&e0));
+        OT_HIP(hipEventCreate(&e1));
+        auto time_it = [&](const std::function<void()> &f) {
+            f();
+            OT_HIP(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3; ++rep) f();
+            OT_HIP(hipEventRecord(e1, s));
+            OT_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            OT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return ms;
+        };
+        const int cand[] = {0, 4, 8, 16, 32};
+        float best_b = 1e30f, best_o = 1e30f;
+        for (int c : cand) {
+            if (c > K + 1) continue;
+            const float tb = time_it([&] { launch_btilde(st, probe, c); });
+            if (tb < best_b) { best_b = tb; tb_b = c; }
+        }
+        for (int c : cand) {
+            if (c > K) continue;
+            const float to = time_it([&] { launch_out(st, probe, tmpm, c); });
+            if (to < best_o) { best_o = to; tb_o = c; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st->opt.verbose)
+            fprintf(stderr, "  pseudo-Schur blocking (%s): M^-1 B~ pass %d levels/thread (%.1f us), output pass %d "
+                    "(%.1f us)\n", sizeof(T) == 8 ? "FP64" : "FP32", tb_b, 1000.0f * best_b / 3, tb_o,
+                    1000.0f * best_o / 3);
     }
 
     // time-line tridiagonal solve of n cells: one wavefront per cell with a
@@ -946,6 +1037,18 @@ struct SimplePrec : PrecBase {
         return st->red.fetch(out, 1)[0];
     }
 
+    // (a . b, a . c) with one host wait
+    void dot2(ot_state *st, const double *a, const double *b, const double *c, double *ab, double *ac) {
+        double *out = st->sums.p + 7 * (K + 2);
+        const int nblk = std::min(256, std::max(1, ceil_div((int64_t)mrho, BS)));
+        k_seg_dot_partial<double><<<dim3(nblk, 1), BS, 0, st->stream>>>(a, b, (int)mrho, st->red.part);
+        k_seg_dot_partial<double><<<dim3(nblk, 1), BS, 0, st->stream>>>(a, c, (int)mrho, st->red.part.p + nblk);
+        k_seg_final<<<2, BS, 0, st->stream>>>(st->red.part, nblk, out);
+        const double *h = st->red.fetch(out, 2);
+        *ab = h[0];
+        *ac = h[1];
+    }
+
     // PCG on P X P^T y = b (b consistent), y = 0 start; returns iterations
     int pcg(ot_state *st, const double *b, double tol, int maxit) {
         hipStream_t s = st->stream;
@@ -964,10 +1067,10 @@ struct SimplePrec : PrecBase {
             const double alpha = rz / pq;
             k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, alpha, p, 1.0, y);
             k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -alpha, q, 1.0, r);
-            const double rn = std::sqrt(std::max(dot(st, r, r), 0.0));
-            if (rn <= tol * bn) break;
             tri(st, r, z);
-            const double rz2 = dot(st, r, z);
+            double rr2, rz2;
+            dot2(st, r, r, z, &rr2, &rz2);                 // one host wait for both
+            if (std::sqrt(std::max(rr2, 0.0)) <= tol * bn) break;
             k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, 1.0, z, rz2 / rz, p);
             rz = rz2;
         }
@@ -1015,12 +1118,19 @@ struct SimplePrec : PrecBase {
 
 namespace otbb {
 
+// the preconditioner in use: OT_PREC_HYBRID is BB until it switches to SIMPLE
+static int active_preconditioner(const ot_state *st) {
+    if (st->opt.preconditioner == OT_PREC_HYBRID) return st->hybrid_simple ? OT_PREC_SIMPLE : OT_PREC_BB;
+    return st->opt.preconditioner;
+}
+
 static void ensure_prec(ot_state *st) {
-    const int kind = 2 * st->opt.preconditioner + (st->opt.preconditioner == OT_PREC_SIMPLE ? OT_FP64 : st->opt.precision);
+    const int pc = active_preconditioner(st);
+    const int kind = 2 * pc + (pc == OT_PREC_SIMPLE ? OT_FP64 : st->opt.precision);
     if (st->prec && st->prec_kind == kind) return;
     std::unique_ptr<PrecBase> &slot = st->precs[kind];
     if (!slot) {
-        if (st->opt.preconditioner == OT_PREC_SIMPLE) slot.reset(new SimplePrec());
+        if (pc == OT_PREC_SIMPLE) slot.reset(new SimplePrec());
         else if (st->opt.precision == OT_MIXED) slot.reset(new BBPrec<float>());
         else slot.reset(new BBPrec<double>());
     }
@@ -1271,6 +1381,25 @@ static int newton_step(ot_state *st, double *res_before) {
     OT_HIP(hipStreamSynchronize(s));
     st->acc.seconds_setup += now_s() - ts;
     solve_with_retry(st, fn, false, true);
+    if (st->opt.preconditioner == OT_PREC_HYBRID && !st->hybrid_simple) {
+        // BB degrades as mu -> 0 (Sec. 4.4.4); SIMPLE stays robust there
+        // (Sec. 4.3, Sec. 4.5).  A BB solve that misses eps_out with a
+        // direction the positivity line search would cut below
+        // hybrid_alpha (an inaccurate direction: a converged one with a short
+        // step is the Newton step itself), or that ends above accept_relres,
+        // hands this system and the rest of the continuation to SIMPLE.
+        const double a = st->last_converged ? 1.0 : trial_alpha(st, st->sol);
+        if (a < st->opt.hybrid_alpha || !(st->last_relres <= st->opt.accept_relres)) {
+            if (st->opt.verbose)
+                fprintf(stderr, "  BB direction: fgmres %d relres %.2e step %.3f -> switching to SIMPLE\n",
+                        st->last_iters, st->last_relres, a);
+            st->hybrid_simple = true;
+            st->acc.linear_systems--;          // the same Newton system, solved again
+            linearize(st);
+            solve_with_retry(st, fn, false, true);
+        }
+    }
+    if (active_preconditioner(st) == OT_PREC_SIMPLE) st->acc.simple_systems++;
     int rc = OT_OK;
     if (!st->last_converged) {
         st->acc.failures++;
@@ -1431,7 +1560,9 @@ void check_options(const ot_options &o) {
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
                OT_EINVAL, "bad iteration caps");
     OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
-    OT_REQUIRE(o.preconditioner == OT_PREC_BB || o.preconditioner == OT_PREC_SIMPLE, OT_EINVAL, "bad preconditioner");
+    OT_REQUIRE(o.preconditioner == OT_PREC_BB || o.preconditioner == OT_PREC_SIMPLE || o.preconditioner == OT_PREC_HYBRID,
+               OT_EINVAL, "bad preconditioner");
+    OT_REQUIRE(o.hybrid_alpha >= 0.0 && o.hybrid_alpha <= 1.0, OT_EINVAL, "hybrid_alpha must be in [0, 1]");
     OT_REQUIRE(o.mem_kind == OT_HOST || o.mem_kind == OT_DEVICE, OT_EINVAL, "bad mem_kind");
 }
 
@@ -1543,11 +1674,13 @@ void ot_options_default(ot_options *o) {
     o->mu0 = 1.0; o->mu_factor = 0.2; o->frac_to_boundary = 0.99; o->final_tol = 0.0; o->mu_stop = 0.0;
     o->accept_relres = 1e-2;
     o->eps_out_min = 1e-10;
-    o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 60; o->inner_restart = 30;
+    o->max_fgmres = 400; o->restart = 400; o->max_inner = 200; o->max_newton = 20; o->inner_restart = 30;
     o->max_inner_S = 10;
     o->max_seconds = 0.0;
     o->neighborhood = 0.0;
-    o->preconditioner = OT_PREC_BB;
+    o->preconditioner = OT_PREC_HYBRID;
+    o->hybrid_alpha = 0.5;
+    o->batch_streams = 8;
     o->step_rule = OT_STEP_COMMON;
     o->precision = OT_MIXED; o->mem_kind = OT_HOST; o->verbose = 0; o->stream = nullptr;
 }
@@ -1718,6 +1851,7 @@ int ot_state_import(ot_state *st, const double *phi, const double *rho, const do
         copy_in(st->s, s, st->mrho, mk, st->stream);
         st->mu = mu;
         st->lin_valid = false;
+        st->hybrid_simple = false;
         OT_HIP(hipStreamSynchronize(st->stream));
     });
 }
@@ -1755,6 +1889,7 @@ int ot_newton_step(ot_state *st, ot_stats *stats, double *res_norm) {
             stats->newton_steps -= before.newton_steps;
             stats->failures -= before.failures;
             stats->tightenings -= before.tightenings;
+            stats->simple_systems -= before.simple_systems;
         }
         if (rc != OT_OK) set_last_error("FGMRES did not reach eps_out");
     });
@@ -1861,6 +1996,7 @@ int ot_state_solve(ot_state *st, double tol, ot_stats *stats) {
             stats->prec_applies -= before.prec_applies;
             stats->failures -= before.failures;
             stats->tightenings -= before.tightenings;
+            stats->simple_systems -= before.simple_systems;
             stats->seconds_total -= before.seconds_total;
             stats->seconds_linear -= before.seconds_linear;
             stats->seconds_setup -= before.seconds_setup;
@@ -1878,11 +2014,53 @@ int ot_solve_batched(int32_t nprob, const ot_mesh *const *meshes, const double *
     int rc = OT_OK;
     int g = guard([&] {
         OT_REQUIRE(nprob >= 0 && (nprob == 0 || (meshes && rho_in && rho_f && K)), OT_EINVAL, "null argument");
-        for (int p = 0; p < nprob; ++p) {
-            int r = ot_solve(meshes[p], rho_in[p], rho_f[p], K[p], tol, opt, rho_out ? rho_out[p] : nullptr,
-                             phi_out ? phi_out[p] : nullptr, costs ? costs + p : nullptr, stats ? stats + p : nullptr);
-            if (r != OT_OK && rc == OT_OK) rc = r;
+        ot_options o;
+        if (opt) o = *opt; else ot_options_default(&o);
+        check_options(o);
+        OT_REQUIRE(o.batch_streams >= 0, OT_EINVAL, "batch_streams must be >= 0");
+        if (nprob == 0) return;
+        int dev = 0;
+        OT_HIP(hipGetDevice(&dev));
+        // inputs may have been produced on the caller's stream
+        OT_HIP(hipStreamSynchronize((hipStream_t)o.stream));
+        // Members run concurrently, each on a stream of its own driven by one
+        // host thread (the Krylov solvers wait on scalars between launches,
+        // so one thread per in-flight member keeps the device fed); each
+        // member has its own state and its own convergence.
+        const int nw = std::max(1, std::min<int>(nprob, o.batch_streams > 0 ? o.batch_streams : 8));
+        std::vector<int> rcs(nprob, OT_OK);
+        std::vector<std::string> msgs(nprob);
+        std::atomic<int> next{0};
+        auto worker = [&]() {
+            hipStream_t s = nullptr;
+            if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+                for (int p; (p = next++) < nprob;) { rcs[p] = OT_EDEVICE; msgs[p] = "stream creation failed"; }
+                return;
+            }
+            ot_options om = o;
+            om.stream = s;
+            for (int p; (p = next++) < nprob;) {
+                rcs[p] = ot_solve(meshes[p], rho_in[p], rho_f[p], K[p], tol, &om, rho_out ? rho_out[p] : nullptr,
+                                  phi_out ? phi_out[p] : nullptr, costs ? costs + p : nullptr,
+                                  stats ? stats + p : nullptr);
+                if (rcs[p] != OT_OK) msgs[p] = ot_last_error();
+            }
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        };
+        if (nw == 1) {
+            worker();
+        } else {
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
+            for (auto &th : pool) th.join();
         }
+        for (int p = 0; p < nprob; ++p)
+            if (rcs[p] != OT_OK) {
+                rc = rcs[p];
+                set_last_error("member " + std::to_string(p) + ": " + msgs[p]);
+                break;
+            }
     });
     return g != OT_OK ? g : rc;
 }
@@ -1953,15 +2131,31 @@ int otbb_debug_schur_apply(ot_state *st, const double *z, double *out) {
                    [&](const double *a, double *b) { st->prec->schur_apply_d(st, a, b); });
 }
 
+int otbb_debug_set_schur_mg(double omega, int32_t nu, int32_t coarse_its, double alpha) {
+    return guard([&] {
+        OT_REQUIRE(omega > 0.0 && omega <= 1.0, OT_EINVAL, "omega must be in (0, 1]");
+        OT_REQUIRE(nu >= 1 && nu <= 16, OT_EINVAL, "nu must be in [1, 16]");
+        OT_REQUIRE(coarse_its >= 1 && coarse_its <= 200, OT_EINVAL, "coarse_its must be in [1, 200]");
+        OT_REQUIRE(alpha > 0.0 && alpha <= 3.0, OT_EINVAL, "alpha must be in (0, 3]");
+        g_smg.omega = omega; g_smg.nu = nu; g_smg.coarse_its = coarse_its; g_smg.alpha = alpha;
+    });
+}
+
 int otbb_debug_set_schur_blocking(int32_t elem_bytes, int32_t btilde_levels, int32_t out_levels) {
     return guard([&] {
-        OT_REQUIRE(btilde_levels >= 0 && btilde_levels <= 64 && out_levels >= 0 && out_levels <= 64, OT_EINVAL,
-                   "levels per thread must be in [0, 64]");
+        const bool reset = btilde_levels < 0 && out_levels < 0;
+        OT_REQUIRE(reset || (btilde_levels >= 0 && btilde_levels <= 64 && out_levels >= 0 && out_levels <= 64),
+                   OT_EINVAL, "levels per thread must be in [0, 64] (or both negative: autotune)");
         OT_REQUIRE(elem_bytes == 0 || elem_bytes == 4 || elem_bytes == 8, OT_EINVAL, "elem_bytes must be 0, 4 or 8");
         for (int r = 0; r < 2; ++r) {
             if (elem_bytes != 0 && elem_bytes != (r ? 8 : 4)) continue;
+            if (reset) {
+                g_schur_tb_fixed[r] = false;
+                continue;
+            }
             g_schur_tb[r][0] = btilde_levels;
             g_schur_tb[r][1] = out_levels;
+            g_schur_tb_fixed[r] = true;
         }
     });
 }

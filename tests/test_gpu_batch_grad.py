@@ -59,6 +59,41 @@ def test_solve_batched(precision, tol):
         assert np.abs(out["rho"][i] - single["rho"]).max() <= 1e-12 * np.abs(single["rho"]).max()
 
 
+CFG4_SMALL = [0, 1, 3, 4, 6, 10, 14, 16]          # members of the 32-problem batch with n <= 48
+
+
+def test_batch_of_the_32_problem_spec_concurrent_vs_sequential():
+    """Eight members of the 32-problem batch (n 32 or 48, K 8 or 16, 1-4
+    Gaussians): the concurrent batch (4 streams) equals the sequential one
+    member by member (each member runs the same kernels on its own stream),
+    and the 32^2, K = 8 member equals the oracle (mixed path, 1e-5)."""
+    import time
+    meshes, ris, rfs, Ks = [], [], [], []
+    for p in CFG4_SMALL:
+        n, K, ri, rf = otinputs.config_marginals(4, p)
+        meshes.append(ot.Mesh.structured(n))
+        ris.append(ri)
+        rfs.append(rf)
+        Ks.append(K)
+    _say(f"[cfg4 subset] members {[otinputs.batch_spec(p) for p in CFG4_SMALL]}")
+    t0 = time.perf_counter()
+    seq = ot.solve_batched(meshes, ris, rfs, Ks, tol=1e-6, batch_streams=1)
+    t1 = time.perf_counter()
+    con = ot.solve_batched(meshes, ris, rfs, Ks, tol=1e-6, batch_streams=4)
+    t2 = time.perf_counter()
+    _say(f"  sequential {t1 - t0:.2f}s, 4 streams {t2 - t1:.2f}s (x{(t1 - t0) / (t2 - t1):.2f})")
+    assert seq["rc"] == ot.OT_OK and con["rc"] == ot.OT_OK
+    for i in range(len(CFG4_SMALL)):
+        assert con["cost"][i] == seq["cost"][i]
+        assert np.array_equal(con["rho"][i], seq["rho"][i])
+    j = CFG4_SMALL.index(10)
+    n, K, ri, rf = otinputs.config_marginals(4, 10)
+    ref = solve_ipm(Problem(structured_mesh(n), K, ri, rf), tol=1e-6).cost
+    err = abs(con["cost"][j] - ref) / ref
+    _say(f"  member 10 (n={n}, K={K}) cost rel err vs oracle {err:.2e}")
+    assert err < 1e-5
+
+
 def _otcost(ri, rf, mesh, K, opts):
     a = torch.tensor(ri, dtype=torch.float64, device="cuda", requires_grad=True)
     b = torch.tensor(rf, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -99,3 +134,51 @@ def test_otcost_autograd():
             err = abs(fd - an) / max(abs(an), 1e-3 * np.abs(g).max())
             _say(f"  FD rho_{side}: fd {fd:.6e} analytic {an:.6e} rel {err:.1e}")
             assert err < 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_gradient_fd_member_of_the_differentiable_batch():
+    """A member of the differentiable batch (128^2, K = 32, mixed path):
+    ot_gradient against central differences along mass-preserving
+    directions of rho_in and rho_f, for the cost of the relaxed problem at
+    mu = 1.6e-3 (the continuation stopped there with mu_stop, that mu solved
+    to |F| <= 1e-10).  The perturbed problems start from the unperturbed
+    solution (ot_state_import) and are solved at the same mu to the same
+    residual; the solution of the relaxed system is unique, so this changes
+    the path, not the result.  Below mu ~ 1e-4 the Newton systems of this
+    size need hundreds of FGMRES iterations each, which puts eight
+    perturbed solves beyond a test's time; the full continuation's gradient
+    is checked against the oracle and finite differences at 8^2 above.
+    Step 1e-4: the cost is accurate to about 1e-10 and the quotient needs it
+    to a few units of eps^2."""
+    n, K, ri, rf = otinputs.config_marginals(5, 0)
+    mesh = ot.Mesh.structured(n)
+    mu_stop = 1.6e-3 * (1 + 1e-9)
+    opts = dict(precision="mixed", final_tol=1e-10, mu_stop=mu_stop)
+    _say(f"[gradient FD n={n} K={K} mu_stop {mu_stop:.3e}]")
+    st = ot.State(mesh, ri, rf, K, **opts)
+    rc, stats = st.solve(1e-6)
+    gi, gf = st.gradient()
+    phi, rho, s, mu = st.export()
+    assert abs(mu - 1.6e-3) < 1e-12
+    _say(f"  base cost {stats.cost:.12g} newton {stats.newton_steps} simple systems {stats.simple_systems}")
+    ac = np.full(mesh.n_coarse, 0.5 / (n // 2) ** 2)              # coarse triangle areas
+    eps = 1e-4
+
+    def cost(a, b):
+        p = ot.State(mesh, a, b, K, **opts)
+        p.import_(phi, rho, s, mu)
+        rc2, st2 = p.solve(1e-6)
+        assert abs(st2.mu - mu) < 1e-15
+        return st2.cost
+
+    for side, r0, g in (("in", ri, gi), ("f", rf, gf)):
+        for d in otinputs.mass_preserving_directions(r0, ac, 2, seed=51 if side == "in" else 52):
+            assert abs(ac @ d) < 1e-14
+            plus = (ri + eps * d, rf) if side == "in" else (ri, rf + eps * d)
+            minus = (ri - eps * d, rf) if side == "in" else (ri, rf - eps * d)
+            fd = (cost(*plus) - cost(*minus)) / (2 * eps)
+            an = float(g @ d)
+            err = abs(fd - an) / max(abs(an), 1e-3 * np.abs(g).max())
+            _say(f"  FD rho_{side}: fd {fd:.6e} analytic {an:.6e} rel {err:.1e}")
+            assert err < 1e-3

@@ -178,7 +178,7 @@ def test_schur_operator_time_blocks(K, precision, tol, levels):
     try:
         _schur_blocks_case(K, precision, tol, levels)
     finally:
-        ot.check(ot.lib().otbb_debug_set_schur_blocking(w, 16, 0 if w == 4 else 16))
+        ot.check(ot.lib().otbb_debug_set_schur_blocking(w, -1, -1))          # back to the autotuner
 
 
 def _schur_blocks_case(K, precision, tol, levels):

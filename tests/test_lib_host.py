@@ -42,10 +42,12 @@ def test_option_defaults():
     o = ot.options()
     assert (o.tol, o.eps_out, o.eps_in_S) == (1e-6, 1e-5, 1e-1)
     assert (o.mu0, o.mu_factor, o.frac_to_boundary) == (1.0, 0.2, 0.99)
-    assert (o.max_fgmres, o.max_inner, o.max_inner_S, o.max_newton) == (400, 200, 10, 60)
+    assert (o.max_fgmres, o.max_inner, o.max_inner_S, o.max_newton) == (400, 200, 10, 20)
     assert (o.eps_in_A, o.restart, o.inner_restart, o.accept_relres) == (1e-6, 400, 30, 1e-2)
     assert (o.mu_stop, o.final_tol, o.step_rule) == (0.0, 0.0, 0)
     assert o.precision == ot.OT_MIXED and o.mem_kind == ot.OT_HOST
+    assert (o.eps_out_min, o.max_seconds, o.neighborhood) == (1e-10, 0.0, 0.0)
+    assert (o.preconditioner, o.hybrid_alpha, o.batch_streams) == (ot.OT_PREC_HYBRID, 0.5, 8)
 
 
 def test_kernel_timing_selection_codes():
@@ -63,6 +65,15 @@ def test_schur_blocking_knob_codes():
     assert L.otbb_debug_set_schur_blocking(4, 65, 0) == ot.OT_EINVAL
     assert L.otbb_debug_set_schur_blocking(4, 16, 0) == 0     # the defaults
     assert L.otbb_debug_set_schur_blocking(8, 16, 16) == 0
+
+
+def test_schur_mg_knob_codes():
+    ot, L = _lib()
+    assert L.otbb_debug_set_schur_mg(0.0, 2, 6, 1.0) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_mg(0.5, 0, 6, 1.0) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_mg(0.5, 2, 0, 1.0) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_mg(0.5, 2, 6, 3.5) == ot.OT_EINVAL
+    assert L.otbb_debug_set_schur_mg(0.5, 2, 6, 1.0) == 0      # the defaults
 
 
 def test_bench_refuses_several_gpus():
