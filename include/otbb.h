@@ -67,6 +67,7 @@ extern "C" {
 #define OT_PREC_BB     0   /* BB block-triangular preconditioner (Sec. 4.4.3) */
 #define OT_PREC_SIMPLE 1   /* SIMPLE preconditioner (Sec. 4.3), FP64       */
 #define OT_PREC_HYBRID 2   /* BB, handing over to SIMPLE when BB degrades  */
+#define OT_PREC_PRIMAL 3   /* primal-Schur preconditioner (Sec. 4.2), FP64 */
 
 #define OT_HOST   0
 #define OT_DEVICE 1
@@ -155,8 +156,8 @@ typedef struct {
                                 rho s >= gamma mu (a neighbourhood of the
                                 central path, keeping the next Newton system
                                 well scaled); 0 (default): positivity only */
-    int32_t preconditioner;  /* OT_PREC_HYBRID (default), OT_PREC_BB or
-                                OT_PREC_SIMPLE.  OT_PREC_HYBRID uses BB until
+    int32_t preconditioner;  /* OT_PREC_HYBRID (default), OT_PREC_BB,
+                                OT_PREC_SIMPLE or OT_PREC_PRIMAL.  OT_PREC_HYBRID uses BB until
                                 a Newton system whose BB solve misses eps_out
                                 with a direction that the positivity line
                                 search would cut below hybrid_alpha, or ends
@@ -170,7 +171,14 @@ typedef struct {
                                 by PCG to eps_in_S (cap max_inner) with its
                                 exact time-line tridiagonal part as
                                 preconditioner, x = u - Diag(A)^-1 B^T P^T y;
-                                always FP64 (precision applies to BB)      */
+                                always FP64 (precision applies to BB).
+                                OT_PREC_PRIMAL: the primal-Schur
+                                factorisation of Sec. 4.2 with the diagonal
+                                C kept in the (2,2) block, S_p = A + B^T P^T
+                                C^-1 P B solved by PCG to eps_in_S (cap
+                                max_inner) with one V-cycle of the K+1
+                                Laplacian multigrid as preconditioner;
+                                always FP64                                 */
     double hybrid_alpha;     /* step-length threshold of OT_PREC_HYBRID
                                 (default 0.5)                               */
     int32_t batch_streams;   /* ot_solve_batched: members solved at once,

@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import (OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG, OT_ELINSOLVE, OT_ENEWTON,  # noqa: F401
                    OT_EDEVICE, OT_ENOMEM, OT_ETIME, OT_FP64, OT_MIXED, OT_HOST, OT_DEVICE, OT_PREC_BB,
-                   OT_PREC_SIMPLE, OT_PREC_HYBRID, OTError, Options, Stats, check, lib)
+                   OT_PREC_SIMPLE, OT_PREC_HYBRID, OT_PREC_PRIMAL, OTError, Options, Stats, check, lib)
 
 __all__ = ["Mesh", "State", "solve", "solve_batched", "options", "OTCost", "OTError", "Stats",
            "kprof_select", "kprof_read", "KPROF"]
@@ -60,7 +60,7 @@ def options(**kw):
         if k == "precision" and isinstance(v, str):
             v = {"mixed": OT_MIXED, "fp64": OT_FP64}[v]
         if k == "preconditioner" and isinstance(v, str):
-            v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE, "hybrid": OT_PREC_HYBRID}[v]
+            v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE, "hybrid": OT_PREC_HYBRID, "primal": OT_PREC_PRIMAL}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
@@ -178,7 +178,7 @@ class State:
             if k == "precision" and isinstance(v, str):
                 v = {"mixed": OT_MIXED, "fp64": OT_FP64}[v]
             if k == "preconditioner" and isinstance(v, str):
-                v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE, "hybrid": OT_PREC_HYBRID}[v]
+                v = {"bb": OT_PREC_BB, "simple": OT_PREC_SIMPLE, "hybrid": OT_PREC_HYBRID, "primal": OT_PREC_PRIMAL}[v]
             setattr(self.opt, k, v)
         check(lib().ot_state_set_options(self._h, C.byref(self.opt)))
 

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libotbb.so")
 OT_OK, OT_EINVAL, OT_EMESH, OT_EMASS, OT_ENEG = 0, -1, -2, -3, -4
 OT_ELINSOLVE, OT_ENEWTON, OT_EDEVICE, OT_ENOMEM, OT_ETIME = -5, -6, -7, -8, -9
 OT_FP64, OT_MIXED = 0, 1
-OT_PREC_BB, OT_PREC_SIMPLE, OT_PREC_HYBRID = 0, 1, 2
+OT_PREC_BB, OT_PREC_SIMPLE, OT_PREC_HYBRID, OT_PREC_PRIMAL = 0, 1, 2, 3
 OT_HOST, OT_DEVICE = 0, 1
 
 ERROR_NAMES = {

@@ -34,6 +34,19 @@ struct StateView {
     const double *phi, *rho, *s, *rin, *rf;
 };
 
+// ------------------------------------------------------------ XCD locality
+// The dispatcher places workgroup b (linear id) on XCD b % 8, and each XCD
+// has its own L2.  For a grid row of gx blocks (gx % 8 == 0, so block
+// (x, y) sits on XCD x % 8 for every row y), this renumbers x so that every
+// XCD takes one contiguous band of gx / 8 blocks: cells with nearby indices
+// then share an L2, and the halos of gathered neighbour data are fetched
+// by one XCD instead of by two at every block boundary.  Any other gx keeps
+// the identity.
+__device__ __forceinline__ int xcd_band_block() {
+    const int gx = gridDim.x, bx = blockIdx.x;
+    return (gx & 7) ? bx : (bx & 7) * (gx >> 3) + (bx >> 3);
+}
+
 // ---------------------------------------------------------------- reductions
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -202,7 +215,7 @@ __device__ __forceinline__ double ptx_at(const double *xr, const double *cs, dou
 __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__ xphi,
                              const double *__restrict__ xr, const double *__restrict__ cs,
                              double *__restrict__ y) {
-    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    const int i = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     if (i >= m.nf) return;
     const int K = S.K, nc = m.nc;
     const double *xp = xphi ? xphi + (size_t)k * m.nf : nullptr;
@@ -236,7 +249,7 @@ __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__
 __global__ void k_opB(MeshView m, StateView S, const double *__restrict__ xphi,
                       const double *__restrict__ xr, const double *__restrict__ cs, double cfac,
                       double *__restrict__ u, double *__restrict__ part) {
-    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    const int j = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     double v = 0.0;
     if (j < m.nc) {
         const double *x0 = xphi + (size_t)k * m.nf, *x1 = x0 + m.nf;
@@ -270,6 +283,24 @@ __global__ void k_proj_fix(const double *__restrict__ ac, int nc, const double *
                            double area, T *__restrict__ y) {
     const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
     if (j < nc) y[(size_t)k * nc + j] -= (T)(ac[j] * us[k] / area);
+}
+
+// diagonal of C = M' Diag(rho)^-1 Diag(s): c[k nc + j] = a'_j s / rho
+__global__ void k_c_diag(int nc, const double *__restrict__ ac, StateView S, double *__restrict__ c) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j >= nc) return;
+    const size_t q = (size_t)k * nc + j;
+    c[q] = ac[j] * S.s[q] / S.rho[q];
+}
+
+// y = M x for a small dense n x n matrix M (row-major); one block
+__global__ void k_small_gemv(int n, const double *__restrict__ M, const double *__restrict__ x,
+                             double *__restrict__ y) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = 0.0;
+        for (int l = 0; l < n; ++l) v += M[(size_t)i * n + l] * x[l];
+        y[i] = v;
+    }
 }
 
 // y^k -= sums[k] * scale   (P^T or mean removal)
@@ -407,7 +438,7 @@ __global__ void k_schur_lift(MeshView m, int K, const T *__restrict__ z, T *__re
 template <typename T>
 __global__ void k_schur_btilde(MeshView m, int K, double dt, const T *__restrict__ z, const T *__restrict__ u,
                                const T *__restrict__ g, T *__restrict__ v) {
-    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    const int i = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     if (i >= m.nf) return;
     double acc = 0.0;
     for (int t = 0; t < m.wo; ++t) {
@@ -438,7 +469,7 @@ template <typename T>
 __global__ void k_schur_out(MeshView m, int K, double dt, const T *__restrict__ z, const T *__restrict__ v,
                             const T *__restrict__ g, const T *__restrict__ wc, const T *__restrict__ rhoT,
                             const T *__restrict__ sT, T *__restrict__ out) {
-    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    const int j = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     if (j >= m.nc) return;
     const size_t q = (size_t)k * m.nc + j;
     const T *zk = z + (size_t)k * m.nc;
@@ -482,7 +513,7 @@ template <typename T>
 __global__ void __launch_bounds__(BS) k_schur_btilde_tb(MeshView m, int K, int kb, double dt, const T *__restrict__ z,
                                                         const T *__restrict__ u, const T *__restrict__ g,
                                                         T *__restrict__ v) {
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = xcd_band_block() * BS + threadIdx.x;
     if (i >= m.nf) return;
     const int k0 = blockIdx.y * kb, k1 = min(K + 1, k0 + kb);
     int oc[kTbWO];
@@ -535,7 +566,7 @@ __global__ void __launch_bounds__(BS) k_schur_out_tb(MeshView m, int K, int kb, 
                                                      const T *__restrict__ v, const T *__restrict__ g,
                                                      const T *__restrict__ wc, const T *__restrict__ rhoT,
                                                      const T *__restrict__ sT, T *__restrict__ out) {
-    const int j = blockIdx.x * BS + threadIdx.x;
+    const int j = xcd_band_block() * BS + threadIdx.x;
     if (j >= m.nc) return;
     const int k0 = blockIdx.y * kb, k1 = min(K, k0 + kb);
     int ce[kTbWCC], cn[kTbWCC];
@@ -903,7 +934,7 @@ __global__ void k_cheb_init(LevelView L, const T *__restrict__ w, const T *__res
 template <typename T, int FINE = 0>
 __global__ void k_cheb_step(LevelView L, const T *__restrict__ w, const T *__restrict__ dinv, T *__restrict__ x,
                             T *__restrict__ r, const T *__restrict__ d, T *__restrict__ dn, double c1, double c2) {
-    const int i = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    const int i = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     if (i >= L.n) return;
     const size_t q = (size_t)k * L.n + i;
     const double ad = lap_row(L, w + (size_t)k * L.ne, d + (size_t)k * L.n, i);

@@ -560,19 +560,12 @@ struct BBPrec : PrecBase {
         return v;
     }
 
-    // linearisation: FP32/FP64 copies of the coefficients, multigrid
-    // hierarchy weights, probed time-line tridiagonal factors
-    void setup(ot_state *st) override {
-        if (nf == 0) alloc(st);
+    // the K+1 rho~-weighted Laplacians: gradients g, multigrid edge weights
+    // of every level and their inverse diagonals
+    void lap_setup(ot_state *st) {
         const ot_mesh *m = st->mesh;
         hipStream_t s = st->stream;
-        MeshView mv = mesh_view(m);
-        StateView sv = st->view();
-        k_lin_edges<T><<<grid2(ne, K + 1), BS, 0, s>>>(mv, sv, g, lw[0]);
-        if (nce > 0) k_lin_cedges<T><<<grid2(nce, K), BS, 0, s>>>(mv, sv, wc);
-        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->rho, rhoT, mrho);
-        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->s, sT, mrho);
-        if (tb_b < 0) autotune_schur_blocking(st);
+        k_lin_edges<T><<<grid2(ne, K + 1), BS, 0, s>>>(mesh_view(m), st->view(), g, lw[0]);
         for (int l = 0; l < nlev; ++l) {
             const MGLevelDev &L = m->lv[l];
             if (l > 0) {
@@ -582,6 +575,21 @@ struct BBPrec : PrecBase {
             }
             k_mg_diag<T><<<grid2(L.n, K + 1), BS, 0, s>>>(lview(m, l), lw[l], ldinv[l]);
         }
+    }
+
+    // linearisation: FP32/FP64 copies of the coefficients, multigrid
+    // hierarchy weights, probed time-line tridiagonal factors
+    void setup(ot_state *st) override {
+        if (nf == 0) alloc(st);
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        MeshView mv = mesh_view(m);
+        StateView sv = st->view();
+        lap_setup(st);
+        if (nce > 0) k_lin_cedges<T><<<grid2(nce, K), BS, 0, s>>>(mv, sv, wc);
+        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->rho, rhoT, mrho);
+        k_convert<T, double><<<grid1(mrho), BS, 0, s>>>(st->s, sT, mrho);
+        if (tb_b < 0) autotune_schur_blocking(st);
         // probe the block-tridiagonal pseudo-Schur operator for its three
         // time diagonals at every coarse cell
         const int ncol = m->h.ncolor;
@@ -964,13 +972,15 @@ struct BBPrec : PrecBase {
 // complement S~ = -(C + B D^-1 B^T), projected); x = u - D^-1 B^T P^T y.
 // The inner system is symmetric positive semidefinite with the per-slice
 // constants as kernel and a consistent right-hand side; it is solved by PCG
-// to eps_in_S (cap max_inner) with the exact time-line tridiagonal part of
-// C + B D^-1 B^T as preconditioner (probed, like the pseudo-Schur time
-// diagonals of the BB preconditioner).
+// to eps_in_S (cap max_inner) preconditioned by the exact time-line
+// tridiagonal part T of C + B D^-1 B^T (probed, like the pseudo-Schur time
+// diagonals of the BB preconditioner), applied in the form consistent with
+// the projection (ctri).
 struct SimplePrec : PrecBase {
     int nf = 0, nc = 0, K = 0;
     size_t nphi = 0, mrho = 0;
     DBuf<double> dA, u, tphi, bu, v, y, r, z, p, q, w, probe, d0, dl, du, inv_dd, lm, up, zsum;
+    DBuf<double> gmat, ginv, lam;              // K x K slice coupling of the constrained time-line solve
 
     void alloc(ot_state *st) {
         const ot_mesh *m = st->mesh;
@@ -980,6 +990,8 @@ struct SimplePrec : PrecBase {
         for (DBuf<double> *b : {&bu, &v, &y, &r, &z, &p, &q, &w, &probe, &d0, &dl, &du, &inv_dd, &lm, &up})
             b->alloc(mrho);
         zsum.alloc(K + 2);
+        gmat.alloc((size_t)K * K);
+        lam.alloc(K + 2);
     }
 
     // out = (C + B D^-1 B^T) P^T x (project = true) or (C + B D^-1 B^T) x,
@@ -1020,6 +1032,67 @@ struct SimplePrec : PrecBase {
                 k_probe_scatter<double><<<gc, BS, 0, s>>>(nc, K, m->color, tc, c, q, d0, dl, du);
             }
         k_tri_factor<double><<<grid1(nc, 1 << 20), BS, 0, s>>>(nc, K, d0, dl, du, inv_dd, lm, up);
+        // G[l][k] = a'^T (T^-1 a'_l)^k, a'_l the coarse areas on slice l: the
+        // slice coupling of the constrained time-line solve (ctri)
+        for (int l = 0; l < K; ++l) {
+            k_fill<double><<<grid1(mrho), BS, 0, s>>>(probe, mrho, 0.0);
+            OT_HIP(hipMemcpyAsync(probe.p + (size_t)l * nc, m->ac, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+            tri(st, probe, q);
+            slice_sums<double>(st, q.p, m->ac, nc, K, gmat.p + (size_t)l * K);
+        }
+        std::vector<double> G((size_t)K * K);
+        OT_HIP(hipMemcpyAsync(G.data(), gmat.p, G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        OT_HIP(hipStreamSynchronize(s));
+        ginv.upload(spd_inverse(G, K), s);
+        OT_HIP(hipStreamSynchronize(s));
+    }
+
+    // Inverse of a small symmetric positive definite matrix (row-major) by
+    // Cholesky; G above is SPD because T is (a principal part of the SPD
+    // C + B D^-1 B^T) and the a'_l are independent.
+    static std::vector<double> spd_inverse(const std::vector<double> &A, int n) {
+        std::vector<double> L((size_t)n * n, 0.0), X((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+                for (int q = 0; q < j; ++q) v -= L[(size_t)i * n + q] * L[(size_t)j * n + q];
+                if (i == j) {
+                    OT_REQUIRE(v > 0.0, OT_ELINSOLVE, "SIMPLE: slice coupling of the time-line solve not positive");
+                    L[(size_t)i * n + i] = std::sqrt(v);
+                } else {
+                    L[(size_t)i * n + j] = v / L[(size_t)j * n + j];
+                }
+            }
+        for (int c = 0; c < n; ++c) {               // solve L L^T x = e_c
+            std::vector<double> y(n, 0.0);
+            for (int i = 0; i < n; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+                for (int q = 0; q < i; ++q) v -= L[(size_t)i * n + q] * y[q];
+                y[i] = v / L[(size_t)i * n + i];
+            }
+            for (int i = n - 1; i >= 0; --i) {
+                double v = y[i];
+                for (int q = i + 1; q < n; ++q) v -= L[(size_t)q * n + i] * X[(size_t)q * n + c];
+                X[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+            }
+        }
+        return X;
+    }
+
+    // Time-line preconditioner made consistent with the projection: for r in
+    // range(P), x = T^-1 (r - a' lam) with lam = G^-1 (a'^T T^-1 r), so that
+    // a'^T x^k = 0 on every slice (x in range(P^T), where P X P^T acts as
+    // P X).  The plain T^-1 ignores the projection and leaves PCG several
+    // times slower on P X P^T.
+    void ctri(ot_state *st, const double *rr, double *x) {
+        hipStream_t s = st->stream;
+        const ot_mesh *m = st->mesh;
+        tri(st, rr, x);
+        slice_sums<double>(st, x, m->ac, nc, K, zsum.p);
+        k_small_gemv<<<1, BS, 0, s>>>(K, ginv, zsum, lam);
+        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(rr, w, mrho);
+        k_proj_fix<double><<<grid2(nc, K), BS, 0, s>>>(m->ac, nc, lam, 1.0, w);
+        tri(st, w, x);
     }
 
     void tri(ot_state *st, const double *rr, double *x) {
@@ -1056,7 +1129,7 @@ struct SimplePrec : PrecBase {
         k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(b, r, mrho);
         const double bn = std::sqrt(std::max(dot(st, r, r), 0.0));
         if (bn == 0.0) return 0;
-        tri(st, r, z);
+        ctri(st, r, z);
         k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(z, p, mrho);
         double rz = dot(st, r, z);
         int it = 0;
@@ -1067,7 +1140,7 @@ struct SimplePrec : PrecBase {
             const double alpha = rz / pq;
             k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, alpha, p, 1.0, y);
             k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -alpha, q, 1.0, r);
-            tri(st, r, z);
+            ctri(st, r, z);
             double rr2, rz2;
             dot2(st, r, r, z, &rr2, &rz2);                 // one host wait for both
             if (std::sqrt(std::max(rr2, 0.0)) <= tol * bn) break;
@@ -1116,6 +1189,141 @@ struct SimplePrec : PrecBase {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Primal-Schur preconditioner (Sec. 4.2) on the projected system, FP64
+// ---------------------------------------------------------------------------
+// The block factorisation on S_p = A + B^T P^T C^-1 P B with the diagonal
+// C kept in the (2,2) block: the exact inverse of [[A, B^T P^T], [P B, -C]],
+// which differs from J_P only in C - P C P^T.  P^-1 (f; g):
+// t = f + B^T P^T C^-1 g made zero-sum per slice; x solves S_p x = t by PCG
+// to eps_in_S (cap max_inner), zero-sum per slice (S_p has the per-slice
+// constants as kernel); y = C^-1 (P B x - g).  The paper solves S_p with
+// AGMG; here one V-cycle of the K+1 rho~-weighted Laplacian multigrid of
+// the BB preconditioner (which sees A, not B^T P^T C^-1 P B) preconditions
+// the PCG.  A negative control: S_p is an anisotropic space-time operator
+// whose time coupling the Laplacian multigrid does not see.
+struct PrimalPrec : BBPrec<double> {
+    DBuf<double> cdg, t, xs, pr2, pz2, pp2, pq2, ub, vr;
+
+    void alloc_primal(ot_state *st) {
+        cdg.alloc(mrho); ub.alloc(mrho); vr.alloc(mrho);
+        for (DBuf<double> *b : {&t, &xs, &pr2, &pz2, &pp2, &pq2}) b->alloc(nphi);
+    }
+
+    void setup(ot_state *st) override {
+        if (nf == 0) {
+            alloc(st);
+            alloc_primal(st);
+        }
+        lap_setup(st);
+        k_c_diag<<<grid2(nc, K), BS, 0, st->stream>>>(nc, st->mesh->ac, st->view(), cdg);
+    }
+
+    // out = P B x (out has m_rho entries)
+    void pb(ot_state *st, const double *x, double *out) {
+        const ot_mesh *m = st->mesh;
+        hipStream_t s = st->stream;
+        dim3 gc = grid2(nc, K);
+        k_opB<<<gc, BS, 0, s>>>(mesh_view(m), st->view(), x, nullptr, nullptr, 0.0, out, st->red.part);
+        double *us = st->sums.p + 4 * (K + 2);
+        k_seg_final<<<K, BS, 0, s>>>(st->red.part, gc.x, us);
+        k_proj_fix<double><<<gc, BS, 0, s>>>(m->ac, nc, us, st->area, out);
+    }
+
+    // out = xphi-part A x + B^T P^T v (x may be null: B^T P^T v only)
+    void saddle_phi(ot_state *st, const double *x, const double *v, double *out) {
+        const ot_mesh *m = st->mesh;
+        double *cs = st->sums.p + 5 * (K + 2);
+        slice_sums<double>(st, v, m->ac, nc, K, cs);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mesh_view(m), st->view(), x, v, cs, out);
+    }
+
+    // out = S_p x = A x + B^T P^T C^-1 P B x
+    void sp_apply(ot_state *st, const double *x, double *out) {
+        pb(st, x, ub);
+        k_dscale<double><<<grid1(mrho), BS, 0, st->stream>>>(mrho, cdg, 1, ub, vr);
+        saddle_phi(st, x, vr, out);
+    }
+
+    void zero_sum(ot_state *st, double *x) {
+        double *bs = st->sums.p + 6 * (K + 2);
+        slice_sums<double>(st, x, nullptr, nf, K + 1, bs);
+        k_slice_shift<double><<<grid2(nf, K + 1), BS, 0, st->stream>>>(nf, bs, 1.0 / nf, x);
+    }
+
+    double dot(ot_state *st, const double *a, const double *b) {
+        double *out = st->sums.p + 7 * (K + 2);
+        const int nblk = std::min(256, std::max(1, ceil_div((int64_t)nphi, BS)));
+        k_seg_dot_partial<double><<<dim3(nblk, 1), BS, 0, st->stream>>>(a, b, (int)nphi, st->red.part);
+        k_seg_final<<<1, BS, 0, st->stream>>>(st->red.part, nblk, out);
+        return st->red.fetch(out, 1)[0];
+    }
+
+    // one V-cycle of the Laplacian multigrid, zero-sum per slice
+    void prec(ot_state *st, const double *r, double *z) {
+        pcg_prec(st, r, z);
+        zero_sum(st, z);
+    }
+
+    // PCG on S_p x = b (b zero-sum per slice), x = 0 start; returns iterations
+    int sp_pcg(ot_state *st, const double *b, double *x, double tol, int maxit) {
+        hipStream_t s = st->stream;
+        k_fill<double><<<grid1(nphi), BS, 0, s>>>(x, nphi, 0.0);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(b, pr2, nphi);
+        const double bn = std::sqrt(std::max(dot(st, pr2, pr2), 0.0));
+        if (bn == 0.0) return 0;
+        prec(st, pr2, pz2);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(pz2, pp2, nphi);
+        double rz = dot(st, pr2, pz2);
+        int it = 0;
+        for (it = 1; it <= maxit; ++it) {
+            sp_apply(st, pp2, pq2);
+            const double pq = dot(st, pp2, pq2);
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, alpha, pp2, 1.0, x);
+            k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, -alpha, pq2, 1.0, pr2);
+            if (std::sqrt(std::max(dot(st, pr2, pr2), 0.0)) <= tol * bn) break;
+            prec(st, pr2, pz2);
+            const double rz2 = dot(st, pr2, pz2);
+            k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, 1.0, pz2, rz2 / rz, pp2);
+            rz = rz2;
+        }
+        return std::min(it, maxit);
+    }
+
+    void apply(ot_state *st, const double *rin, double *zout) override {
+        hipStream_t s = st->stream;
+        const double *f = rin, *g = rin + nphi;
+        // t = f + B^T P^T C^-1 g, zero-sum per slice
+        k_dscale<double><<<grid1(mrho), BS, 0, s>>>(mrho, cdg, 1, g, vr);
+        saddle_phi(st, nullptr, vr, t);
+        k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, 1.0, f, 1.0, t);
+        zero_sum(st, t);
+        st->acc.inner_S_iters += sp_pcg(st, t, xs, st->opt.eps_in_S, st->opt.max_inner);
+        zero_sum(st, xs);
+        // y = C^-1 (P B x - g)
+        pb(st, xs, ub);
+        k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -1.0, g, 1.0, ub);
+        k_dscale<double><<<grid1(mrho), BS, 0, s>>>(mrho, cdg, 1, ub, zout + nphi);
+        k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(xs, zout, nphi);
+        st->acc.prec_applies++;
+    }
+
+    // component access of the BB preconditioner: not part of this one
+    void schur_apply_d(ot_state *, const double *, double *) override { unsupported(); }
+    int schur_solve_d(ot_state *, const double *, double *, double, int) override { unsupported(); return 0; }
+    void tri_diagonals_d(ot_state *, double *, double *, double *) override { unsupported(); }
+    void tri_solve_d(ot_state *, const double *, double *) override { unsupported(); }
+    int laplace_solve_d(ot_state *, const double *, double *, double, int) override { unsupported(); return 0; }
+    void vcycle_d(ot_state *, const double *, double *) override { unsupported(); }
+    size_t level_data_d(ot_state *, int, int, double *) override { unsupported(); return 0; }
+    static void unsupported() {
+        throw OtError(OT_EINVAL, "inspection call of the BB preconditioner on a state using the primal-Schur "
+                                 "preconditioner");
+    }
+};
+
 namespace otbb {
 
 // the preconditioner in use: OT_PREC_HYBRID is BB until it switches to SIMPLE
@@ -1126,11 +1334,13 @@ static int active_preconditioner(const ot_state *st) {
 
 static void ensure_prec(ot_state *st) {
     const int pc = active_preconditioner(st);
-    const int kind = 2 * pc + (pc == OT_PREC_SIMPLE ? OT_FP64 : st->opt.precision);
+    const bool fp64_only = pc == OT_PREC_SIMPLE || pc == OT_PREC_PRIMAL;
+    const int kind = 2 * pc + (fp64_only ? OT_FP64 : st->opt.precision);
     if (st->prec && st->prec_kind == kind) return;
     std::unique_ptr<PrecBase> &slot = st->precs[kind];
     if (!slot) {
         if (pc == OT_PREC_SIMPLE) slot.reset(new SimplePrec());
+        else if (pc == OT_PREC_PRIMAL) slot.reset(new PrimalPrec());
         else if (st->opt.precision == OT_MIXED) slot.reset(new BBPrec<float>());
         else slot.reset(new BBPrec<double>());
     }
@@ -1560,7 +1770,8 @@ void check_options(const ot_options &o) {
                    o.max_newton >= 1 && o.inner_restart >= 2 && o.inner_restart < kMaxBasis,
                OT_EINVAL, "bad iteration caps");
     OT_REQUIRE(o.precision == OT_FP64 || o.precision == OT_MIXED, OT_EINVAL, "bad precision");
-    OT_REQUIRE(o.preconditioner == OT_PREC_BB || o.preconditioner == OT_PREC_SIMPLE || o.preconditioner == OT_PREC_HYBRID,
+    OT_REQUIRE(o.preconditioner == OT_PREC_BB || o.preconditioner == OT_PREC_SIMPLE ||
+                   o.preconditioner == OT_PREC_HYBRID || o.preconditioner == OT_PREC_PRIMAL,
                OT_EINVAL, "bad preconditioner");
     OT_REQUIRE(o.hybrid_alpha >= 0.0 && o.hybrid_alpha <= 1.0, OT_EINVAL, "hybrid_alpha must be in [0, 1]");
     OT_REQUIRE(o.mem_kind == OT_HOST || o.mem_kind == OT_DEVICE, OT_EINVAL, "bad mem_kind");

@@ -120,6 +120,15 @@ def _translation_state(n, K, shift=0.3):
     return prob, phi, rho, np.ones_like(rho)
 
 
+def _lap_pinv_solve(L, b):
+    """L^+ b for a connected graph Laplacian L and b orthogonal to the
+    constants: the zero-mean solution, from the system grounded at node 0."""
+    L = sp.csc_matrix(L)
+    x = np.zeros(L.shape[0])
+    x[1:] = spla.spsolve(L[1:, 1:], b[1:])
+    return x - x.mean()
+
+
 def _commutator_ratio(prob, phi, rho, variant):
     """Relative gap between A^+ B^T y and -M^-1 B~ A~^+ M' y on a smooth,
     zero-mass y (the approximation the BB preconditioner rests on), compared
@@ -127,8 +136,6 @@ def _commutator_ratio(prob, phi, rho, variant):
     o, K = prob.ops, prob.K
     _, B, _ = kkt_blocks(prob, phi, rho, np.ones_like(rho))
     rt = edge_density(prob, rho)
-    Ap = [np.linalg.pinv(o.laplacian(rt[k]).toarray(), rcond=1e-12) for k in range(K + 1)]
-    Atp = [np.linalg.pinv(o.coarse_laplacian(rho[k]).toarray(), rcond=1e-12) for k in range(K)]
     Bt = btilde(prob, phi)
     if variant == "flip":
         # misread: transport part of B~ with the opposite sign
@@ -141,8 +148,11 @@ def _commutator_ratio(prob, phi, rho, variant):
     t = np.arange(1, K + 1) / (K + 1)
     y = proj_t(prob, np.outer(np.sin(np.pi * t), np.cos(np.pi * cx[:, 0]) * np.cos(np.pi * cx[:, 1])))
     BTy = (B.T @ y.ravel()).reshape(K + 1, -1)
-    Y = np.stack([Ap[k] @ BTy[k] for k in range(K + 1)])
-    w = np.stack([Atp[k] @ (o.ac * y[k]) for k in range(K)])
+    # both right-hand sides are orthogonal to the constants: 1^T (B^T y)^k
+    # pairs y with B 1_k, a multiple of a' per slice, and a'^T y^k = 0
+    assert np.abs(BTy.sum(axis=1)).max() < 1e-10 * np.abs(BTy).max()
+    Y = np.stack([_lap_pinv_solve(o.laplacian(rt[k]), BTy[k]) for k in range(K + 1)])
+    w = np.stack([_lap_pinv_solve(o.coarse_laplacian(rho[k]), o.ac * y[k]) for k in range(K)])
     X = -(Bt @ w.ravel()).reshape(K + 1, -1) / o.a[None, :]
     X = X - X.mean(1, keepdims=True)
     Y = Y - Y.mean(1, keepdims=True)
