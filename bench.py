@@ -1,7 +1,8 @@
-"""Benchmark: BB-preconditioned interior-point solve of the 256 x 256
-right-triangle grid with K = 64 on one MI355X (5-Gaussian-mixture marginals
-plus a 1e-3 background, synthetic), mixed precision (FP32 BB preconditioner,
-FP64 Newton residual / FGMRES / update) against the FP64 path.
+"""Benchmark: interior-point solve of the 256 x 256 right-triangle grid with
+K = 64 on one MI355X (5-Gaussian-mixture marginals plus a 1e-3 background,
+synthetic), mixed precision (FP32 BB preconditioner, FP64 Newton residual /
+FGMRES / update) against the FP64 path; default preconditioner (BB, handing
+over to SIMPLE for the late mu).
 
 What is timed
   * time to tolerance, once per precision: the interior-point continuation
@@ -13,10 +14,11 @@ What is timed
   * steps: one step is one inexact Newton step (residual, linearisation,
     BB-preconditioned FGMRES, recovery, line search, update) of the mixed
     path from a fixed iterate.  The iterates are snapshots taken by the
-    mixed continuation at the start of every mu it reached (the converged
-    iterate of the previous mu with mu reduced, i.e. the first Newton system
-    of each interior-point step), used in turn, so the timed steps cover the
-    early and the late systems.  W untimed steps, then exactly K timed ones
+    mixed continuation at the start of every mu it reached while still on
+    BB (the converged iterate of the previous mu with mu reduced, i.e. the
+    first Newton system of each interior-point step), used in turn, so the
+    timed steps cover the early and the late BB systems.  W untimed steps,
+    then exactly K timed ones
     bracketed by device synchronisations; value = FGMRES (Krylov)
     iterations per second over them.  A deadline stops the loop early (the
     line then says how many steps ran) so that the line is always printed.
@@ -46,7 +48,7 @@ COPY_BYTES = 1 << 30          # reference copy of the counter loop: 1 GiB read, 
 # counters read for the 1 GiB reference copy (fetch x2.0000, write x1.0000);
 # profiles/k_schur_out_256x256_K64_traffic.md.  Valid only for the kernel
 # version those runs measured, on the 256 x 256, K = 64 workload.
-TRAFFIC_BYTES = {("schur_out", 3): 73632.9 * 1024 * 2.0 + 8192.0 * 1024 * 1.0}
+TRAFFIC_BYTES = {}
 KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 METRIC = "time-to-tol (s) & Krylov iters/s, 256^2 mesh K=64: mixed vs FP64, 1 GPU"
@@ -59,13 +61,17 @@ def parse():
     p.add_argument("--warmup", type=int, default=2, help="untimed Newton steps before the timed ones")
     p.add_argument("--config", type=int, default=3, help="workload: 1, 2, 3 (256^2, K=64) or 5")
     p.add_argument("--kernel", default="schur_out", help="kernel whose roofline is reported")
-    p.add_argument("--budget", type=float, default=480.0,
+    p.add_argument("--budget", type=float, default=540.0,
                    help="wall seconds (from process start) by which the line must be printed")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 time to tolerance")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--tol-only", choices=("mixed", "fp64"), default=None,
                    help="only the time to tolerance of one precision, with the whole budget (no timed steps, "
                         "no CPU sample); prints its own JSON line")
+    p.add_argument("--batch", action="store_true",
+                   help="instead: the 32-problem batch (grid sides 32..128, K 8..32, 1-4 Gaussians) solved by one "
+                        "ot_solve_batched call, mixed precision, default preconditioner; prints its own JSON line")
+    p.add_argument("--batch-streams", type=int, default=8, help="members in flight at once in --batch")
     p.add_argument("--verbose", type=int, default=0)
     p.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--counter-loop", type=int, default=0,
@@ -132,6 +138,40 @@ def counter_loop(a, ot, otinputs, torch):
     print(json.dumps({"counter_loop": a.counter_loop, "copy_bytes": COPY_BYTES, "m_rho": st.m_rho}), flush=True)
 
 
+def run_batch(a, ot, otinputs, torch):
+    """The 32-problem batch through one ot_solve_batched call (mixed, default
+    preconditioner), after an untimed call on its two smallest members."""
+    specs = [otinputs.config_marginals(4, p) for p in range(32)]
+    meshes = {}
+    for n, *_ in specs:
+        if n not in meshes:
+            meshes[n] = ot.Mesh.structured(n)
+    small = sorted(range(32), key=lambda p: specs[p][0] ** 2 * specs[p][1])[:2]
+    ot.solve_batched([meshes[specs[p][0]] for p in small], [specs[p][2] for p in small],
+                     [specs[p][3] for p in small], [specs[p][1] for p in small], tol=1e-6,
+                     batch_streams=a.batch_streams, raise_on_error=False)
+    torch.cuda.synchronize()
+    log("batch warm-up done")
+    t0 = time.perf_counter()
+    out = ot.solve_batched([meshes[n] for n, *_ in specs], [x[2] for x in specs], [x[3] for x in specs],
+                           [x[1] for x in specs], tol=1e-6, batch_streams=a.batch_streams, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = out["stats"]
+    its = sum(x.outer_iters for x in st)
+    serial = sum(x.seconds_total for x in st)
+    print(json.dumps({
+        "metric": "32-problem batch time-to-tol (s)", "value": dt, "unit": "s", "higher_is_better": False,
+        "n_gpus": 1, "rc": out["rc"], "batch_streams": a.batch_streams,
+        "members_ok": int(sum(1 for x in st if x.mu < 1e-6)), "members": 32,
+        "krylov_its": its, "krylov_its_per_s": its / dt, "sum_member_seconds": serial,
+        "members_spec": [[n, K] for n, K, *_ in specs],
+        "member_seconds": [round(x.seconds_total, 3) for x in st],
+        "member_newton": [int(x.newton_steps) for x in st],
+        "member_simple_systems": [int(x.simple_systems) for x in st],
+        "dtype": "f64 + f32 (BB preconditioner kernels)", "data": "synthetic", "wall_s": elapsed()}), flush=True)
+
+
 def main():
     a = parse()
     if a.cpu_sample_only:
@@ -150,6 +190,10 @@ def main():
     dev = torch.device("cuda")
     if a.counter_loop > 0:
         counter_loop(a, ot, otinputs, torch)
+        return
+
+    if a.batch:
+        run_batch(a, ot, otinputs, torch)
         return
 
     n, K, ri, rf = otinputs.config_marginals(a.config)
@@ -228,18 +272,18 @@ def main():
                           "config": {"n": n, "K": K, "config": a.config}, **r, "wall_s": elapsed()}), flush=True)
         return
 
+    # order: mixed continuation (it records the snapshots), the timed steps,
+    # the FP64 continuation, the CPU sample; each stage leaves the later
+    # ones a reserve so that the line is printed within the budget
+    cpu_reserve = 0.0 if a.no_cpu else 25.0
+    step_reserve = 12.0 + 2.5 * (a.steps + a.warmup)
     snaps = []
-    share = 0.38 if not a.no_fp64 else 0.6
-    mixed = time_to_tol("mixed", max(30.0, share * remaining()), snaps)
+    mixed = time_to_tol("mixed", max(30.0, remaining() - step_reserve - cpu_reserve - 15.0), snaps)
     log(f"mixed continuation: {mixed}")
-    fp64 = None
-    if not a.no_fp64:
-        fp64 = time_to_tol("fp64", max(30.0, 0.55 * remaining()))
-        log(f"fp64 continuation: {fp64}")
 
     # timed Newton steps of the mixed path from the snapshots, in turn
     st = state("mixed")
-    deadline = a.budget - 25.0 - (0 if a.no_cpu else 40.0)
+    deadline = a.budget - cpu_reserve - 15.0
     order = list(range(len(snaps))) if snaps else []
 
     def one_step(i):
@@ -266,6 +310,12 @@ def main():
     launches, kms, kbytes = ot.kprof_read()
     ot.kprof_select("none")
     log(f"timed steps: {done} of {a.steps}, {its} FGMRES its in {T:.2f}s")
+    del st
+
+    fp64 = None
+    if not a.no_fp64:
+        fp64 = time_to_tol("fp64", max(30.0, remaining() - cpu_reserve - 10.0))
+        log(f"fp64 continuation: {fp64}")
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     line = {
         "metric": METRIC,
@@ -279,9 +329,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 (residual, FGMRES, update, Laplacian PCG vectors) + f32 (BB preconditioner kernels)",
+        "dtype": "f64 (residual, FGMRES, update, Laplacian PCG vectors, SIMPLE) + f32 (BB preconditioner kernels)",
         "data": "synthetic",
-        "config": {"workload": f"BB-preconditioned interior-point solve, {n}x{n} right-triangle grid "
+        "config": {"workload": f"interior-point solve (BB preconditioner, SIMPLE for late mu), "
+                               f"{n}x{n} right-triangle grid "
                                f"({2 * n * n} fine triangles), K={K}, "
                                + ("5-Gaussian mixtures + 1e-3 background" if a.config == 3 else
                                   f"benchmark configuration {a.config}"),
