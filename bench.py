@@ -47,8 +47,9 @@ COPY_BYTES = 1 << 30          # reference copy of the counter loop: 1 GiB read, 
 # `bench.py --counter-loop 20` (KiB per dispatch), scaled by what the same
 # counters read for the 1 GiB reference copy (fetch x2.0000, write x1.0000);
 # profiles/k_schur_out_256x256_K64_traffic.md.  Valid only for the kernel
-# version those runs measured, on the 256 x 256, K = 64 workload.
-TRAFFIC_BYTES = {}
+# version those runs measured (XCD-banded blocks), on the 256 x 256, K = 64
+# workload.
+TRAFFIC_BYTES = {("schur_out", 3): 47914.7 * 1024 * 2.0 + 8192.0 * 1024 * 1.0}
 KERNEL_NAMES = {"schur_out": "k_schur_out", "schur_btilde": "k_schur_btilde_tb", "cheb_fine": "k_cheb_step<., 1>",
                 "tri_fine": "k_tri_scan<., 1>", "multidot": "k_multidot", "saddle_phi": "k_saddle_phi"}
 METRIC = "time-to-tol (s) & Krylov iters/s, 256^2 mesh K=64: mixed vs FP64, 1 GPU"
@@ -153,8 +154,10 @@ def run_batch(a, ot, otinputs, torch):
     torch.cuda.synchronize()
     log("batch warm-up done")
     t0 = time.perf_counter()
+    # verbose: every member's Newton steps go to stderr (progress of a long call)
     out = ot.solve_batched([meshes[n] for n, *_ in specs], [x[2] for x in specs], [x[3] for x in specs],
-                           [x[1] for x in specs], tol=1e-6, batch_streams=a.batch_streams, raise_on_error=False)
+                           [x[1] for x in specs], tol=1e-6, batch_streams=a.batch_streams, verbose=a.verbose,
+                           raise_on_error=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = out["stats"]

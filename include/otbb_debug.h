@@ -64,10 +64,13 @@ int otbb_debug_tri_solve(ot_state *st, const double *r, double *x);
 /* Time levels per thread of the two time-blocked pseudo-Schur passes for
  * FP32 (elem_bytes 4), FP64 (8) or both (0) operands, for the BB
  * preconditioners created afterwards (process-wide knob; 0 levels = one
- * level per thread).  By default each preconditioner times the candidates
- * 0, 4, 8, 16, 32 on its own mesh and K at its first linearisation and keeps
- * the fastest; this call fixes the values instead, and both values negative
- * returns to the autotuner. */
+ * level per thread).  By default the first preconditioner of a given shape
+ * (mesh sizes, K, precision) in the process times the candidates 0, 4, 8,
+ * 16, 32 at its first linearisation and keeps the fastest, and later ones
+ * of that shape reuse the choice (the blocked and per-level passes round
+ * differently, so results do not depend on which stream timed faster);
+ * this call fixes the values instead, and both values negative returns to
+ * the autotuner. */
 int otbb_debug_set_schur_blocking(int32_t elem_bytes, int32_t btilde_levels, int32_t out_levels);
 /* V-cycle of the pseudo-Schur multigrid (Sec. 4.4.3 solves that system
  * iteratively; the multigrid is this library's own) for the BB

@@ -26,6 +26,11 @@ struct MeshView {
     const int *eK, *eL, *erK, *erL, *ceI, *ceJ, *cf_edge, *cf_nb, *fo_c, *co_f, *cr_e, *cc_edge, *cc_nb;
     const int *cr_k, *cr_l;     // R_T slots resolved: potential cells of the edge
     const double *cr_g;         // R_T slots resolved: 0.5 cr_w / d_e
+    const double *cr_g2;        // R_T slots resolved: 0.5 cr_w / d_e^2
+    // fine-cell edge slots resolved (slot t of cell i, [t nf + i]): density
+    // sides of the edge, lambda, 0.5 |e| / d_e, tw_e
+    const int *cf_rk, *cf_rl;
+    const double *cf_lam, *cf_bw, *cf_tw;
 };
 
 struct StateView {
@@ -222,17 +227,22 @@ __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__
     const double *ph = S.phi + (size_t)k * m.nf;
     const double xi = xp ? xp[i] : 0.0;
     double v = 0.0;
+    const double phi_i = ph[i];
     for (int t = 0; t < m.wf; ++t) {
-        const int e = m.cf_edge[t * m.nf + i];
-        if (e < 0) break;
-        const int nb = m.cf_nb[t * m.nf + i];
-        if (xp) v += m.etw[e] * rho_edge(m, S, k, e) * (xi - xp[nb]);
-        const double sgn = (m.eK[e] == i) ? 1.0 : -1.0;
-        const int rK = m.erK[e], rL = m.erL[e];
-        const double lam = m.elam[e];
+        const int q = t * m.nf + i;
+        if (m.cf_edge[q] < 0) break;
+        const int nb = m.cf_nb[q];
+        const int rK = m.cf_rk[q], rL = m.cf_rl[q];
+        const double lam = m.cf_lam[q];
+        if (xp) {
+            const double mK = 0.5 * (rho_at(S, nc, k, rK) + rho_at(S, nc, k + 1, rK));
+            const double mL = 0.5 * (rho_at(S, nc, k, rL) + rho_at(S, nc, k + 1, rL));
+            v += m.cf_tw[q] * (lam * mK + (1.0 - lam) * mL) * (xi - xp[nb]);
+        }
+        // sgn_e (grad phi)_e = (phi_i - phi_nb) / d_e whichever side i is on
         const double wK = ptx_at(xr, cs, S.area, K, nc, k - 1, rK) + ptx_at(xr, cs, S.area, K, nc, k, rK);
         const double wL = ptx_at(xr, cs, S.area, K, nc, k - 1, rL) + ptx_at(xr, cs, S.area, K, nc, k, rL);
-        v += 0.5 * sgn * m.elen[e] * grad_phi(m, ph, e) * (lam * wK + (1.0 - lam) * wL);
+        v += m.cf_bw[q] * (phi_i - ph[nb]) * (lam * wK + (1.0 - lam) * wL);
     }
     for (int t = 0; t < m.wo; ++t) {
         const int c = m.fo_c[t * m.nf + i];
@@ -259,16 +269,12 @@ __global__ void k_opB(MeshView m, StateView S, const double *__restrict__ xphi,
             if (f < 0) break;
             v += m.co_w[t * m.nc + j] * (x1[f] - x0[f]) / S.dt;
         }
-        double g = 0.0;
         for (int t = 0; t < m.wr; ++t) {
-            const int e = m.cr_e[t * m.nc + j];
-            if (e < 0) break;
-            const int eK = m.eK[e], eL = m.eL[e];
-            const double id = m.einvd[e];
-            g += m.cr_w[t * m.nc + j] * ((p0[eK] - p0[eL]) * (x0[eK] - x0[eL]) +
-                                        (p1[eK] - p1[eL]) * (x1[eK] - x1[eL])) * id * id;
+            const int q = t * m.nc + j;
+            if (m.cr_e[q] < 0) break;
+            const int eK = m.cr_k[q], eL = m.cr_l[q];
+            v += m.cr_g2[q] * ((p0[eK] - p0[eL]) * (x0[eK] - x0[eL]) + (p1[eK] - p1[eL]) * (x1[eK] - x1[eL]));
         }
-        v += 0.5 * g;
         const size_t q = (size_t)k * m.nc + j;
         if (cfac != 0.0) v -= cfac * m.ac[j] * S.s[q] / S.rho[q] * ptx_at(xr, cs, S.area, S.K, m.nc, k, j);
         u[q] = v;

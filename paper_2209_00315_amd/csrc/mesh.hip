@@ -570,15 +570,33 @@ void mesh_finalize(ot_mesh *m) {
     m->fo_c.upload(h.fo_c, s); m->co_f.upload(h.co_f, s); m->cr_e.upload(h.cr_e, s);
     {
         std::vector<int> ck(h.cr_e.size(), 0), cl(h.cr_e.size(), 0);
-        std::vector<double> cg(h.cr_e.size(), 0.0);
+        std::vector<double> cg(h.cr_e.size(), 0.0), cg2(h.cr_e.size(), 0.0);
         for (size_t q = 0; q < h.cr_e.size(); ++q) {
             const int e = h.cr_e[q];
             if (e < 0) continue;
             ck[q] = h.eK[e];
             cl[q] = h.eL[e];
             cg[q] = 0.5 * h.cr_w[q] * invd[e];
+            cg2[q] = 0.5 * h.cr_w[q] * invd[e] * invd[e];
         }
-        m->cr_k.upload(ck, s); m->cr_l.upload(cl, s); m->cr_g.upload(cg, s);
+        m->cr_k.upload(ck, s); m->cr_l.upload(cl, s); m->cr_g.upload(cg, s); m->cr_g2.upload(cg2, s);
+    }
+    {
+        // fine-cell edge slots resolved: density sides, lambda, 0.5 |e| / d_e, tw_e
+        const size_t nq = h.cf_edge.size();
+        std::vector<int> rk(nq, 0), rl(nq, 0);
+        std::vector<double> lam(nq, 0.0), bw(nq, 0.0), tws(nq, 0.0);
+        for (size_t q = 0; q < nq; ++q) {
+            const int e = h.cf_edge[q];
+            if (e < 0) continue;
+            rk[q] = h.erK[e];
+            rl[q] = h.erL[e];
+            lam[q] = h.elam[e];
+            bw[q] = 0.5 * h.elen[e] * invd[e];
+            tws[q] = tw[e];
+        }
+        m->cf_rk.upload(rk, s); m->cf_rl.upload(rl, s);
+        m->cf_lam.upload(lam, s); m->cf_bw.upload(bw, s); m->cf_tw.upload(tws, s);
     }
     m->cc_edge.upload(h.cc_edge, s); m->cc_nb.upload(h.cc_nb, s);
     m->color.upload(h.color, s);

@@ -89,7 +89,9 @@ struct ot_mesh {
     // pseudo-Schur output pass reads them coalesced instead of through the
     // edge index
     otbb::DBuf<int> cr_k, cr_l;
-    otbb::DBuf<double> cr_g;
+    otbb::DBuf<double> cr_g, cr_g2;
+    otbb::DBuf<int> cf_rk, cf_rl;
+    otbb::DBuf<double> cf_lam, cf_bw, cf_tw;
     std::vector<otbb::MGLevelDev> lv;
     std::vector<otbb::SLevelDev> slv;
     double area = 0.0;                 // |Omega| = sum of coarse areas

@@ -7,6 +7,8 @@
 #include <functional>
 #include <map>
 #include <thread>
+#include <tuple>
+#include <type_traits>
 #include <atomic>
 #include <memory>
 #include <mutex>
@@ -79,6 +81,13 @@ constexpr int kUpdateBlocks = 8192;
 // unless otbb_debug_set_schur_blocking has fixed them.
 static int g_schur_tb[2][2] = {{16, 0}, {16, 16}};
 static bool g_schur_tb_fixed[2] = {false, false};
+// Autotuned choices, shared by every preconditioner of the same shape in
+// the process: the blocked and per-level passes round differently, so a
+// choice that depended on each state's own timing (which concurrent
+// streams perturb) would make results depend on scheduling.  Key: n_f,
+// n_c, fine edges, K, FP64 or not.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
 // pseudo-Schur V-cycle parameters of BB preconditioners created afterwards
 // (otbb_debug_set_schur_mg)
 struct SchurMGParams {
@@ -114,7 +123,8 @@ MeshView mesh_view(const ot_mesh *m) {
     v.eK = m->eK; v.eL = m->eL; v.erK = m->erK; v.erL = m->erL; v.ceI = m->ceI; v.ceJ = m->ceJ;
     v.cf_edge = m->cf_edge; v.cf_nb = m->cf_nb; v.fo_c = m->fo_c; v.co_f = m->co_f; v.cr_e = m->cr_e;
     v.cc_edge = m->cc_edge; v.cc_nb = m->cc_nb;
-    v.cr_k = m->cr_k; v.cr_l = m->cr_l; v.cr_g = m->cr_g;
+    v.cr_k = m->cr_k; v.cr_l = m->cr_l; v.cr_g = m->cr_g; v.cr_g2 = m->cr_g2;
+    v.cf_rk = m->cf_rk; v.cf_rl = m->cf_rl; v.cf_lam = m->cf_lam; v.cf_bw = m->cf_bw; v.cf_tw = m->cf_tw;
     return v;
 }
 
@@ -191,6 +201,7 @@ struct ot_state {
     int last_iters = 0;
     double last_relres = 0.0;
     bool last_converged = false;
+    bool no_plateau = false;                   // FGMRES runs to its cap (the retry of a failed solve)
 
     StateView view() const {
         StateView v;
@@ -397,7 +408,7 @@ struct BBPrec : PrecBase {
     DBuf<double> d0, dl, du;
     DBuf<T> inv_dd, lm, up;
     DBuf<T> cT, dT, rhsS, zS, yT, bT, uT, vT, tmpm, tmpm2, tmpm3, probe;
-    DBuf<T> VS, rhsc;                          // inner GMRES basis, scaled rhs
+    DBuf<double> VS, rhsc;                     // inner GMRES basis, scaled rhs (FP64 in both paths)
     // PCG work: the Krylov vectors and the operator are FP64 in both paths;
     // only the V-cycle (vb -> vx) runs in T.  An all-FP32 PCG stalls above
     // the 1e-6 relative residual the outer FGMRES needs at small mu.
@@ -680,6 +691,16 @@ struct BBPrec : PrecBase {
         tb_b = g_schur_tb[r][0];
         tb_o = g_schur_tb[r][1];
         if (g_schur_tb_fixed[r] || !blocking_fits(st->mesh)) return;
+        const auto key = std::make_tuple(nf, nc, ne, K, r);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                tb_b = it->second.first;
+                tb_o = it->second.second;
+                return;
+            }
+        }
         hipStream_t s = st->stream;
         k_fill<T><<<grid1(mrho), BS, 0, s>>>(probe, mrho, (T)1);
         k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mesh_view(st->mesh), K, probe, uT);
@@ -710,6 +731,13 @@ struct BBPrec : PrecBase {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        {
+            // a state of the same shape tuned meanwhile: adopt its choice
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto ins = g_tune_cache.emplace(key, std::make_pair(tb_b, tb_o));
+            tb_b = ins.first->second.first;
+            tb_o = ins.first->second.second;
+        }
         if (st->opt.verbose)
             fprintf(stderr, "  pseudo-Schur blocking (%s): M^-1 B~ pass %d levels/thread (%.1f us), output pass %d "
                     "(%.1f us)\n", sizeof(T) == 8 ? "FP64" : "FP32", tb_b, 1000.0f * best_b / 3, tb_o,
@@ -734,53 +762,84 @@ struct BBPrec : PrecBase {
         tri_launch<1>(st->stream, nc, inv_dd, lm, up, r, x, ev);
     }
 
-    // right-preconditioned restarted GMRES on the pseudo-Schur system; w = 0 start
+    // right-preconditioned restarted GMRES on the pseudo-Schur system; w = 0
+    // start.  The Krylov basis, the scaled right-hand side and the
+    // Gram-Schmidt updates are FP64 in both paths; with T = float only the
+    // operator and the V-cycle run in FP32 (their inputs and outputs are
+    // converted).  An FP32 basis loses orthogonality within a few tens of
+    // iterations when the new direction nearly lies in the span (its norm
+    // after orthogonalisation far below its norm before): on the 256^2,
+    // K = 64 benchmark the outer FGMRES then needed 4-5x the FP64 path's
+    // iterations on the early Newton systems, and more inner iterations
+    // made it worse.
     int gmres_schur(ot_state *st, const T *rhs, T *w, double tol, int maxit) {
         hipStream_t s = st->stream;
         const size_t n = mrho;
+        constexpr bool f64 = std::is_same<T, double>::value;
         k_fill<T><<<grid1(n), BS, 0, s>>>(w, n, (T)0);
         // row scaling by the inverse diagonal: the rows of near-empty cells
         // (s A~ dominated) and of dense cells (rho-weighted time Laplacian)
         // differ by orders of magnitude
-        k_dscale<T><<<grid1(n), BS, 0, s>>>(n, d0, 1, rhs, rhsc);
-        rhs = rhsc;
-        double beta = norm2<T>(st, rhs, n);
+        if constexpr (f64) {
+            k_dscale<double><<<grid1(n), BS, 0, s>>>(n, d0, 1, rhs, rhsc);
+        } else {
+            k_convert<double, T><<<grid1(n), BS, 0, s>>>(rhs, rhsc.p, n);
+            k_dscale<double><<<grid1(n), BS, 0, s>>>(n, d0, 1, rhsc, rhsc);
+        }
+        const double *rs = rhsc.p;
+        double beta = norm2<double>(st, rs, n);
         if (beta == 0.0) return 0;
         const double target = tol * beta;
         Givens G(mS);
         int its = 0;
+        // operator input in T: the FP64 vector itself, or its FP32 copy
+        auto in_T = [&](const double *x) -> const T * {
+            if constexpr (f64) return x;
+            else {
+                k_convert<T, double><<<grid1(n), BS, 0, s>>>(x, tmpm2.p, n);
+                return tmpm2.p;
+            }
+        };
+        // D0^-1 S z into the FP64 vector out
+        auto scaled_apply_to = [&](const T *z, double *out) {
+            if constexpr (f64) s_scaled_apply(st, z, out);
+            else {
+                s_scaled_apply(st, z, tmpm2.p);
+                k_convert<double, T><<<grid1(n), BS, 0, s>>>(tmpm2.p, out, n);
+            }
+        };
         // r = rhs (w = 0)
-        k_convert<T, T><<<grid1(n), BS, 0, s>>>(rhs, VS.p, n);
+        k_convert<double, double><<<grid1(n), BS, 0, s>>>(rs, VS.p, n);
         double res = beta;
         while (its < maxit) {
-            k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 0.0, VS.p, 1.0 / beta, VS.p);
+            k_axpby<double><<<grid1(n), BS, 0, s>>>(n, 0.0, VS.p, 1.0 / beta, VS.p);
             G.reset(beta);
             int j = 0;
             std::vector<double> h(mS + 1);
             for (; j < mS && its < maxit; ++j) {
-                s_prec(st, VS.p + (size_t)j * n, tmpm);
-                T *wn = VS.p + (size_t)(j + 1) * n;
-                s_scaled_apply(st, tmpm, wn);
-                double hn = cgs2<T>(st, VS.p, n, j + 1, wn, n, h.data());
+                s_prec(st, in_T(VS.p + (size_t)j * n), tmpm);
+                double *wn = VS.p + (size_t)(j + 1) * n;
+                scaled_apply_to(tmpm, wn);
+                double hn = cgs2<double>(st, VS.p, n, j + 1, wn, n, h.data());
                 for (int i = 0; i <= j; ++i) G.h(i, j) = h[i];
                 G.h(j + 1, j) = hn;
                 ++its;
                 res = G.push(j);
-                if (hn > 0) k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 0.0, wn, 1.0 / hn, wn);
+                if (hn > 0) k_axpby<double><<<grid1(n), BS, 0, s>>>(n, 0.0, wn, 1.0 / hn, wn);
                 if (res <= target || hn == 0.0) { ++j; break; }
             }
             std::vector<double> y = G.solve(j);
             DBuf<double> &yd = st->shift;      // small device scratch (>= mS)
             OT_HIP(hipMemcpyAsync(yd.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-            k_combine<T, T><<<grid1(n), BS, 0, s>>>(n, VS.p, n, j, yd.p, 0.0, tmpm2);
+            k_combine<double, T><<<grid1(n), BS, 0, s>>>(n, VS.p, n, j, yd.p, 0.0, tmpm2.p);
             s_prec(st, tmpm2, tmpm);
             k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 1.0, tmpm, 1.0, w);
             OT_HIP(hipStreamSynchronize(s));   // y lives in pageable host memory
             if (res <= target || its >= maxit) break;
             // restart: r = D0^-1 (rhs - S w)
-            s_scaled_apply(st, w, VS.p);
-            k_axpby<T><<<grid1(n), BS, 0, s>>>(n, 1.0, rhs, -1.0, VS.p);
-            beta = norm2<T>(st, VS.p, n);
+            scaled_apply_to(w, VS.p);
+            k_axpby<double><<<grid1(n), BS, 0, s>>>(n, 1.0, rs, -1.0, VS.p);
+            beta = norm2<double>(st, VS.p, n);
             if (beta <= target) break;
         }
         return its;
@@ -1432,7 +1491,8 @@ static int fgmres(ot_state *st, const double *b, double *x, double tol_abs, int 
                 // one, where the step is taken anyway: near a converged Newton
                 // iterate the residual meets the rounding floor of the operator
                 // well above eps_out |b|, and the cap would only add time
-                const bool stalled = its >= 80 && res > 0.5 * hist[its - 41] && res <= st->opt.accept_relres * beta0;
+                const bool stalled = !st->no_plateau && its >= 80 && res > 0.5 * hist[its - 41] &&
+                                     res <= st->opt.accept_relres * beta0;
                 if (res <= tol_abs || hn == 0.0 || stalled) { stop = stalled; breakdown = hn == 0.0; ++j; break; }
             }
             // x = x_cycle_start + Z y; the first cycle starts from x = 0
@@ -1544,6 +1604,7 @@ static int solve_newton_system(ot_state *st, double rhs_norm_abs, bool tighten =
 // and stops).  strict: retry whenever eps_out was missed.  The right-hand
 // side is untouched by a solve, so the retry starts from the same system.
 static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = false, bool tighten = false) {
+    st->no_plateau = false;
     solve_newton_system(st, rhs_norm_abs, tighten);
     if (st->last_converged || (!strict && st->last_relres <= st->opt.accept_relres)) return;
     const ot_options saved = st->opt;
@@ -1554,7 +1615,12 @@ static void solve_with_retry(ot_state *st, double rhs_norm_abs, bool strict = fa
     st->opt.eps_in_A = 0.1 * saved.eps_in_A;
     st->opt.max_inner_S = std::max(saved.max_inner_S, saved.max_inner);
     linearize(st);
+    // the retry runs to the iteration cap: a plateau exit of the first
+    // attempt can sit just above accept_relres in the true residual (the
+    // plateau test reads the FGMRES estimate), which fails the step
+    st->no_plateau = true;
     solve_newton_system(st, rhs_norm_abs, tighten);
+    st->no_plateau = false;
     st->acc.linear_systems--;              // one Newton system, two attempts
     if (st->opt.verbose)
         fprintf(stderr, "  retry: fgmres %d relres %.2e -> fgmres %d relres %.2e\n", its1, rr1, st->last_iters,
