@@ -169,9 +169,12 @@ typedef struct {
                                 projected system, u = Diag(A)^-1 c,
                                 P (C + B Diag(A)^-1 B^T) P^T y = P B u - d
                                 by PCG to eps_in_S (cap max_inner) with its
-                                exact time-line tridiagonal part as
-                                preconditioner, x = u - Diag(A)^-1 B^T P^T y;
-                                always FP64 (precision applies to BB).
+                                exact time-line tridiagonal part T as
+                                preconditioner (applied as T^-1 (r - a' l),
+                                l chosen per slice so that the result lies
+                                in the range of P^T), x = u - Diag(A)^-1
+                                B^T P^T y; always FP64 (precision applies to
+                                BB).
                                 OT_PREC_PRIMAL: the primal-Schur
                                 factorisation of Sec. 4.2 with the diagonal
                                 C kept in the (2,2) block, S_p = A + B^T P^T
