@@ -216,10 +216,12 @@ __device__ __forceinline__ double ptx_at(const double *xr, const double *cs, dou
 
 // y_phi^k = A^k x_phi^k + (B^T w)^k with w = P^T x_rho, cs[l] = a'^T x_rho^l:
 // (B^T w)^k = Omega (w^{k-1} - w^k)/dt + 1/2 sum_e sgn len g_e R_E(w^{k-1} + w^k)_e
-// xphi == nullptr drops the A^k x_phi^k term (y = B^T P^T x_rho).
+// xphi == nullptr drops the A^k x_phi^k term (y = B^T P^T x_rho); dscale !=
+// nullptr divides the result by it (entries 0 leave it unscaled), as
+// k_dscale with inv = 1 would in a second pass.
 __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__ xphi,
                              const double *__restrict__ xr, const double *__restrict__ cs,
-                             double *__restrict__ y) {
+                             const double *__restrict__ dscale, double *__restrict__ y) {
     const int i = xcd_band_block() * BS + threadIdx.x, k = blockIdx.y;
     if (i >= m.nf) return;
     const int K = S.K, nc = m.nc;
@@ -250,7 +252,12 @@ __global__ void k_saddle_phi(MeshView m, StateView S, const double *__restrict__
         v += m.fo_w[t * m.nf + i] *
              (ptx_at(xr, cs, S.area, K, nc, k - 1, c) - ptx_at(xr, cs, S.area, K, nc, k, c)) / S.dt;
     }
-    y[(size_t)k * m.nf + i] = v;
+    const size_t q = (size_t)k * m.nf + i;
+    if (dscale) {
+        const double di = dscale[q];
+        v *= di != 0.0 ? 1.0 / di : 1.0;
+    }
+    y[q] = v;
 }
 
 // u^k = (B x_phi)^k - cfac C (P^T x_rho)^k  (C = a' s / rho); cfac = 0 drops C.
@@ -297,6 +304,25 @@ __global__ void k_c_diag(int nc, const double *__restrict__ ac, StateView S, dou
     if (j >= nc) return;
     const size_t q = (size_t)k * nc + j;
     c[q] = ac[j] * S.s[q] / S.rho[q];
+}
+
+// x += alpha p; r -= alpha q (the two CG updates in one pass)
+__global__ void k_cg_update(size_t n, double alpha, const double *__restrict__ p, const double *__restrict__ q,
+                            double *__restrict__ x, double *__restrict__ r) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+        x[i] = alpha * p[i] + 1.0 * x[i];
+        r[i] = -alpha * q[i] + 1.0 * r[i];
+    }
+}
+
+// w^k = r^k - a' lam[k]
+__global__ void k_sub_slice_cols(int nc, const double *__restrict__ ac, const double *__restrict__ lam,
+                                 const double *__restrict__ r, double *__restrict__ w) {
+    const int j = blockIdx.x * BS + threadIdx.x, k = blockIdx.y;
+    if (j < nc) {
+        const size_t q = (size_t)k * nc + j;
+        w[q] = r[q] - ac[j] * lam[k];
+    }
 }
 
 // y = M x for a small dense n x n matrix M (row-major); one block

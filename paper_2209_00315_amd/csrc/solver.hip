@@ -285,7 +285,7 @@ static void apply_saddle_core(const ot_state *st, const double *x, double *y, do
                              40.0 * h.ne;
         const kprof::Ev ev = kprof::take(OT_KPROF_SADDLE_PHI, 8, bytes);
         hipExtLaunchKernelGGL(k_saddle_phi, grid2(nf, K + 1), dim3(BS), 0, s, ev.a, ev.b, 0, mv, sv, x,
-                              x + st->nphi, (const double *)cs, y);
+                              x + st->nphi, (const double *)cs, (const double *)nullptr, y);
     }
     dim3 gc = grid2(nc, K);
     k_opB<<<gc, BS, 0, s>>>(mv, sv, x, x + st->nphi, cs, 1.0, y + st->nphi, part);
@@ -1063,8 +1063,7 @@ struct SimplePrec : PrecBase {
         double *cs = st->sums.p + 5 * (K + 2);           // a'^T x^k (for P^T x)
         if (project) slice_sums<double>(st, x, m->ac, nc, K, cs);
         else k_fill<double><<<1, BS, 0, s>>>(cs, K + 2, 0.0);
-        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, x, cs, tphi.p);      // B^T P^T x
-        k_dscale<double><<<grid1(nphi), BS, 0, s>>>(nphi, dA, 1, tphi, tphi);               // D^-1
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, x, cs, dA, tphi.p);  // D^-1 B^T P^T x
         dim3 gc = grid2(nc, K);
         k_opB<<<gc, BS, 0, s>>>(mv, sv, tphi, x, cs, -1.0, out, st->red.part);              // B (.) + C P^T x
         if (project) {
@@ -1149,8 +1148,7 @@ struct SimplePrec : PrecBase {
         tri(st, rr, x);
         slice_sums<double>(st, x, m->ac, nc, K, zsum.p);
         k_small_gemv<<<1, BS, 0, s>>>(K, ginv, zsum, lam);
-        k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(rr, w, mrho);
-        k_proj_fix<double><<<grid2(nc, K), BS, 0, s>>>(m->ac, nc, lam, 1.0, w);
+        k_sub_slice_cols<<<grid2(nc, K), BS, 0, s>>>(nc, m->ac, lam, rr, w);
         tri(st, w, x);
     }
 
@@ -1197,8 +1195,7 @@ struct SimplePrec : PrecBase {
             const double pq = dot(st, p, q);
             if (!(pq > 0.0)) break;
             const double alpha = rz / pq;
-            k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, alpha, p, 1.0, y);
-            k_axpby<double><<<grid1(mrho), BS, 0, s>>>(mrho, -alpha, q, 1.0, r);
+            k_cg_update<<<grid1(mrho), BS, 0, s>>>(mrho, alpha, p, q, y, r);
             ctri(st, r, z);
             double rr2, rz2;
             dot2(st, r, r, z, &rr2, &rz2);                 // one host wait for both
@@ -1227,8 +1224,7 @@ struct SimplePrec : PrecBase {
         // x = u - D^-1 B^T P^T y; z = (x; y)
         double *cs = st->sums.p + 5 * (K + 2);
         slice_sums<double>(st, y.p, m->ac, nc, K, cs);
-        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, y, cs, tphi.p);
-        k_dscale<double><<<grid1(nphi), BS, 0, s>>>(nphi, dA, 1, tphi, tphi);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, s>>>(mv, sv, nullptr, y, cs, dA, tphi.p);
         k_convert<double, double><<<grid1(nphi), BS, 0, s>>>(u, zout, nphi);
         k_axpby<double><<<grid1(nphi), BS, 0, s>>>(nphi, -1.0, tphi, 1.0, zout);
         k_convert<double, double><<<grid1(mrho), BS, 0, s>>>(y, zout + nphi, mrho);
@@ -1294,7 +1290,7 @@ struct PrimalPrec : BBPrec<double> {
         const ot_mesh *m = st->mesh;
         double *cs = st->sums.p + 5 * (K + 2);
         slice_sums<double>(st, v, m->ac, nc, K, cs);
-        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mesh_view(m), st->view(), x, v, cs, out);
+        k_saddle_phi<<<grid2(nf, K + 1), BS, 0, st->stream>>>(mesh_view(m), st->view(), x, v, cs, nullptr, out);
     }
 
     // out = S_p x = A x + B^T P^T C^-1 P B x
