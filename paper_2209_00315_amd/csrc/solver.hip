@@ -623,8 +623,6 @@ struct BBPrec : PrecBase {
         hipStream_t s = st->stream;
         MeshView mv = mesh_view(m);
         k_schur_lift<T><<<grid2(nf, K + 1), BS, 0, s>>>(mv, K, z, uT);
-        const double b = sizeof(T), S1 = K + 1;
-        const MeshHost &h = m->h;
         // time-blocked passes (levels per thread; 0 = per-level kernels) when
         // the cell stencils fit their register caps
         const int tb_btilde = blocking_fits(m) ? tb_b : 0, tb_out = blocking_fits(m) ? tb_o : 0;
@@ -1260,7 +1258,7 @@ struct SimplePrec : PrecBase {
 struct PrimalPrec : BBPrec<double> {
     DBuf<double> cdg, t, xs, pr2, pz2, pp2, pq2, ub, vr;
 
-    void alloc_primal(ot_state *st) {
+    void alloc_primal() {
         cdg.alloc(mrho); ub.alloc(mrho); vr.alloc(mrho);
         for (DBuf<double> *b : {&t, &xs, &pr2, &pz2, &pp2, &pq2}) b->alloc(nphi);
     }
@@ -1268,7 +1266,7 @@ struct PrimalPrec : BBPrec<double> {
     void setup(ot_state *st) override {
         if (nf == 0) {
             alloc(st);
-            alloc_primal(st);
+            alloc_primal();
         }
         lap_setup(st);
         k_c_diag<<<grid2(nc, K), BS, 0, st->stream>>>(nc, st->mesh->ac, st->view(), cdg);
