@@ -216,7 +216,34 @@ def central_step(rho, s, drho, ds, gmu, amax):
     return t
 
 
-def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common", neighborhood=0.0):
+def solve_reduced_direct(prob: Problem, phi, rho, s, f, gt):
+    """(delta phi, delta rho) of the Sec. 3.1 system J_s (dphi; drho) =
+    (f; g~), with delta rho eliminated (C is diagonal):
+
+        (A + B^T C^-1 B) dphi = f + B^T C^-1 g~,   drho = C^-1 (B dphi - g~).
+
+    The potential-only matrix is symmetric positive semidefinite with the
+    global constant as kernel (the kernel of J_s); the system is grounded at
+    the first potential unknown like solve_saddle_direct.  Same solution,
+    far less fill in the sparse LU at 64^2 and beyond."""
+    A, B, C = kkt_blocks(prob, phi, rho, s)
+    cinv = 1.0 / C.diagonal()
+    S = (A + B.T @ sp.diags(cinv) @ B).tocsc()
+    rhs = np.ravel(f) + B.T @ (cinv * np.ravel(gt))
+    n = S.shape[0]
+    dphi = np.zeros(n)
+    Sg = S[1:, :][:, 1:].tocsc()
+    lu = spla.splu(Sg, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    dphi[1:] = lu.solve(rhs[1:])
+    if not np.all(np.isfinite(dphi)) or np.linalg.norm(Sg @ dphi[1:] - rhs[1:]) > 1e-11 * max(
+            np.linalg.norm(rhs[1:]), 1e-300):
+        dphi[1:] = spla.splu(Sg).solve(rhs[1:])
+    drho = cinv * (B @ dphi - np.ravel(gt))
+    return dphi, drho
+
+
+def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common", neighborhood=0.0,
+                direct="saddle"):
     """One Newton update of (phi, rho, s) at fixed mu with a direct solve.
 
     step_rule "common" (the reading of the positivity line search of Sec. 2.4):
@@ -225,13 +252,22 @@ def newton_step(prob: Problem, phi, rho, s, mu, tau=0.99, step_rule="common", ne
     keeps rho positive, s the one that keeps s positive (a primal / dual split
     of that line search).  neighborhood = gamma > 0 (common rule only)
     shortens the step further so that rho s >= gamma mu holds in every cell
-    that satisfied it before (a neighbourhood of the central path)."""
+    that satisfied it before (a neighbourhood of the central path).
+    direct "saddle" solves J_s as it stands, "reduced" through the
+    potential-only system of solve_reduced_direct (same solution)."""
     K, nf, nc = prob.K, prob.nf, prob.nc
     f, g, h, gt = newton_rhs(prob, phi, rho, s, mu)
-    J = saddle_matrix(prob, phi, rho, s)
-    x = solve_saddle_direct(J, np.concatenate([f.ravel(), gt.ravel()]))
-    dphi = x[: (K + 1) * nf].reshape(K + 1, nf)
-    drho = x[(K + 1) * nf:].reshape(K, nc)
+    if direct == "reduced":
+        dphi, drho = solve_reduced_direct(prob, phi, rho, s, f, gt)
+        dphi = dphi.reshape(K + 1, nf)
+        drho = drho.reshape(K, nc)
+    elif direct == "saddle":
+        J = saddle_matrix(prob, phi, rho, s)
+        x = solve_saddle_direct(J, np.concatenate([f.ravel(), gt.ravel()]))
+        dphi = x[: (K + 1) * nf].reshape(K + 1, nf)
+        drho = x[(K + 1) * nf:].reshape(K, nc)
+    else:
+        raise ValueError(f"unknown direct solver {direct}")
     ds = (h - s * drho) / rho
     a_p, a_d = step_length(rho, drho, tau), step_length(s, ds, tau)
     alpha = min(a_p, a_d)
@@ -270,14 +306,15 @@ def initial_point(prob: Problem, mu0=1.0):
 
 def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
               max_newton=20, final_tol=None, start=None, mu_start=None,
-              max_mu_steps=200, mu_target=None, step_rule="common", neighborhood=0.0):
+              max_mu_steps=200, mu_target=None, step_rule="common", neighborhood=0.0, direct="saddle"):
     """IP continuation: for mu_l = mu0 mu_factor^l, Newton until |F_mu| <= tol,
     warm-started from the previous mu; stop after the first mu < tol.
 
     final_tol, when given, replaces tol for the last mu (tighter solves for
     parity and finite-difference checks).  start = (phi, rho, s) and mu_start
     resume a previous run.  mu_target, when given, clamps the schedule at that
-    value and stops after solving it (solutions at a prescribed mu).
+    value and stops after solving it (solutions at a prescribed mu).  direct
+    selects the Newton systems' direct solver (newton_step).
     """
     t0 = time.perf_counter()
     m0 = float(prob.ops.ac @ prob.rho_in)
@@ -306,7 +343,7 @@ def solve_ipm(prob: Problem, tol=1e-6, mu0=1.0, mu_factor=0.2, tau=0.99,
                 break
             if it == max_newton:
                 break
-            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau, step_rule, neighborhood)
+            phi, rho, s, _ = newton_step(prob, phi, rho, s, mu, tau, step_rule, neighborhood, direct)
             rho = renormalize(prob, rho, m0)
             count += 1
         newton_counts.append(count)

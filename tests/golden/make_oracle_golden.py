@@ -34,18 +34,22 @@ WORKLOADS = {
     "cfg2_64x64_K32": lambda: otinputs.config_marginals(2),
     "bg_32x32_K16": lambda: (32, 16) + otinputs.mixture_pair(32, 5, 3, background=1e-3),
 }
+# direct solver of the Newton systems (oracle.ipm.newton_step): at 64^2,
+# K = 32 the sparse LU of the full saddle system does not finish in hours,
+# the potential-only elimination takes about 30 s per system
+DIRECT = {"cfg2_64x64_K32": "reduced", "bg_32x32_K16": "saddle"}
 
 
 def make(name):
     n, K, ri, rf = WORKLOADS[name]()
     prob = Problem(structured_mesh(n), K, ri, rf)
     t0 = time.perf_counter()
-    r = solve_ipm(prob, tol=1e-6, final_tol=1e-10, max_newton=40)
+    r = solve_ipm(prob, tol=1e-6, final_tol=1e-10, max_newton=40, direct=DIRECT[name])
     dt = time.perf_counter() - t0
     if not r.converged:
         raise RuntimeError(f"oracle did not converge on {name}")
     path = os.path.join(HERE, f"oracle_{name}.npz")
-    meta = dict(n=n, K=K, tol=1e-6, final_tol=1e-10, mu=r.mu, cost=r.cost, dual=r.dual, gap=r.gap,
+    meta = dict(n=n, K=K, tol=1e-6, final_tol=1e-10, direct=DIRECT[name], mu=r.mu, cost=r.cost, dual=r.dual, gap=r.gap,
                 newton_per_mu=[int(c) for c in r.newton_per_mu], seconds=dt)
     np.savez_compressed(path, rho=r.rho.ravel(), phi=r.phi.ravel(), meta=json.dumps(meta))
     print(name, json.dumps(meta), flush=True)

@@ -6,7 +6,7 @@ import pytest
 import otinputs
 from oracle.mesh import structured_mesh, cartesian_mesh
 from oracle.ipm import (Problem, residual, kkt_matrix, solve_ipm, kinetic_energy,
-                        dual_value, residual_norm)
+                        dual_value, residual_norm, initial_point, newton_step)
 
 
 def _random_state(prob, rng):
@@ -275,3 +275,27 @@ def test_translation_w2_convergence():
         errs.append(abs(2 * r.cost - 0.09))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.005
+
+
+def test_reduced_direct_solve_equals_saddle_solve():
+    """Eliminating delta rho through the diagonal C gives the solution of
+    the full reduced saddle system J_s: Newton steps at the start point and
+    at a later iterate agree, and so do whole continuations."""
+    n, K = 8, 4
+    ri, rf = otinputs.mixture_pair(n, 2, config=8, problem=1)
+    prob = Problem(structured_mesh(n), K, ri, rf)
+    p0, r0, s0 = initial_point(prob)
+    it = solve_ipm(prob, tol=1e-6, mu_target=0.04)
+    for phi, rho, s, mu in ((p0, r0, s0, 1.0), (it.phi, it.rho, it.s, 0.008)):
+        a = newton_step(prob, phi, rho, s, mu, direct="saddle")
+        b = newton_step(prob, phi, rho, s, mu, direct="reduced")
+        for xa, xb in zip(a[:3], b[:3]):
+            # phi up to the global constant (the kernel)
+            d = xa - xb
+            d = d - d.mean() if xa.shape[0] == K + 1 else d
+            assert np.abs(d).max() < 1e-9 * np.abs(xa).max()
+        assert abs(a[3] - b[3]) < 1e-12
+    ra = solve_ipm(prob, tol=1e-6, final_tol=1e-10)
+    rb = solve_ipm(prob, tol=1e-6, final_tol=1e-10, direct="reduced")
+    assert abs(ra.cost - rb.cost) < 1e-10 * ra.cost
+    assert np.abs(ra.rho - rb.rho).max() < 1e-8 * np.abs(ra.rho).max()
